@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark: GateKeeper-GPU filter throughput on one MI355X.
+
+Workload (the headline configuration): a 100 Mbp seeded random reference
+(41% GC), 2^24 pairs of 100 bp reads with one candidate each, e = 5; 30% true
+origins with Poisson(5) edits, 70% decoys sharing an exact 12-mer with their
+candidate window.  Reads are 2-bit packed and stored transposed (encoded on
+the GPU before the timed region, as the paper's host-encoded kernel time).
+
+A step is one gk_filter call over the whole batch, inputs resident in HBM.
+Prints one JSON line with pairs/s, the dominant kernel's roofline fraction
+(HIP events around every launch, on the launch stream) and the oracle timed
+on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X peaks used for the roofline.
+CUS, LANES, CLOCK_GHZ = 256, 64, 2.4
+VALU_PEAK_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0      # int32 lane-ops, 39.32 T/s
+HBM_PEAK_GBS = 8000.0
+
+
+def ops_per_pair(m: int, e: int) -> int:
+    """Algorithmic int32 lane-ops per pair: (2e+1) masks x W32 words x 14 ops
+    (2 read-plane funnels, 2 compare, 9 amendment, 1 AND), plus 6 per word
+    and 16 per pair for the window gather, count and stores."""
+    w = (m + 31) // 32
+    return 14 * (2 * e + 1) * w + 6 * w + 16
+
+
+def bytes_per_pair(m: int) -> int:
+    """Algorithmic bytes per pair for one candidate per read: packed read
+    (m/4 B), window (m/4 B), read index + position (8 B), accept + est (3 B),
+    read length (2 B)."""
+    return m // 4 + m // 4 + 8 + 3 + 2
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("gk_filter.hip", "gk_internal.h"):
+        with open(os.path.join(ROOT, "paper_2103_14978_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_hash: str, n_pairs: int):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on this exact kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "k_filter_w4_config1_e5_counters.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_hash or d.get("n_pairs") != n_pairs:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--pairs", type=int, default=1 << 24)
+    ap.add_argument("--e", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="target wall time of the CPU-baseline sample")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(pairs are independent: more GPUs would each filter "
+                                   "their own share of the batch)"}))
+        return 2
+
+    import torch
+    import gen
+    from paper_2103_14978_amd import device, gk
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        return 1
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    m, e, n_pairs = 100, args.e, args.pairs
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    t = time.time()
+    ref = gen.c1_reference()
+    ps = gen.c1_pairs(ref, e, n_pairs=n_pairs)
+    log(f"generated reference + {ps.n_pairs} pairs in {time.time() - t:.1f}s")
+
+    ctx = gk.gk_create(0)
+    t = time.time()
+    gk.gk_load_reference(ctx, ref)
+    log(f"reference resident in {time.time() - t:.2f}s")
+    dr = device.encode_reads(ctx, ps.reads, ps.read_off, max_len=m)
+    dp = device.upload_pairs(ps.pair_read, ps.cand_pos, None, with_bits=False)
+    batch = device.batch_for(dr, dp, e_uniform=e, max_read_len=m)
+    torch.cuda.synchronize()
+    log("inputs resident")
+
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        gk.gk_filter(ctx, batch, stream)
+    torch.cuda.synchronize()
+
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        gk.gk_filter(ctx, batch, stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [s.elapsed_time(x) for s, x in zip(starts, ends)]
+    k_avg_s = float(np.mean(kernel_ms)) / 1e3
+    ms_per_step = wall * 1e3 / args.steps
+    value = n_pairs * args.steps / wall
+    log(f"{args.steps} steps in {wall:.4f}s; kernel avg {k_avg_s * 1e3:.4f} ms "
+        f"(min {min(kernel_ms):.4f}, max {max(kernel_ms):.4f})")
+
+    # Parity on a random sample of this run's outputs (bit-exact).
+    parity = None
+    if not args.no_parity:
+        import oracle
+        a_gpu, s_gpu = device.results(dp)
+        rng = np.random.default_rng(12345)
+        idx = np.sort(rng.choice(n_pairs, size=min(n_pairs, 1 << 15), replace=False))
+        ra, rs = oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read[idx],
+                                     ps.cand_pos[idx], e, n_threads=gen.default_threads())
+        mism = int(np.sum((a_gpu[idx] != ra) | (s_gpu[idx] != rs)))
+        parity = {"sampled_pairs": int(len(idx)), "mismatches": mism,
+                  "accepted_frac": float(np.mean(a_gpu == 1))}
+        log(f"parity sample: {mism} mismatches of {len(idx)}")
+
+    ops = ops_per_pair(m, e) * n_pairs
+    achieved_tops = ops / k_avg_s / 1e12
+    khash = kernel_source_hash()
+    traffic = traffic_from_profile(khash, n_pairs)
+    roofline = {"bound": "alu", "kernel": "k_filter<4>", "achieved": round(achieved_tops, 3),
+                "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
+                "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                "ops_per_pair": ops_per_pair(m, e), "kernel_ms": round(k_avg_s * 1e3, 4),
+                "hbm_alg_GBs": round(bytes_per_pair(m) * n_pairs / k_avg_s / 1e9, 1),
+                "kernel_source_hash": khash}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = gen.default_threads()
+        cal = min(n_pairs, 1 << 15)
+        t = time.perf_counter()
+        oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read[:cal], ps.cand_pos[:cal], e,
+                            n_threads=threads)
+        rate = cal / max(time.perf_counter() - t, 1e-6)
+        sample = int(min(n_pairs, max(cal, rate * args.cpu_seconds)))
+        t = time.perf_counter()
+        oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read[:sample],
+                            ps.cand_pos[:sample], e, n_threads=threads)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(sample / dt, 1), "unit": "pairs/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"first {sample} pairs of the same batch, {threads} threads, "
+                         f"{dt:.1f}s wall"}
+        log(f"cpu baseline {sample / dt:.0f} pairs/s on {threads} threads")
+
+    out = {
+        "metric": "filtered pairs/sec (100bp, e=5) on 1 MI355X, bit-exact",
+        "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"plain filter, {n_pairs} pairs of {m}bp reads, e={e}, "
+                               "100 Mbp GC-41% reference, 30% true / 70% 12-mer decoys, "
+                               "reads 2-bit packed transposed",
+                   "pairs_per_step": n_pairs, "read_len": m, "e": e},
+        "kernel_pairs_per_s": round(n_pairs / k_avg_s, 1),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    gk.gk_destroy(ctx)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

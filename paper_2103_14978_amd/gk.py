@@ -1,0 +1,174 @@
+"""Python binding of libgk (include/gk.h): same names, argument marshalling
+only.  Device buffers are passed as raw device addresses; torch tensors are
+accepted and passed by ``data_ptr()``.  Streams are raw hipStream_t handles
+(``torch.cuda.current_stream().cuda_stream``) or torch streams.
+
+Every step of the filter runs in the HIP library.  This module has no
+fallback: if libgk.so is missing it raises, it never computes anything
+itself.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgk.so")
+
+GK_OK, GK_EINVAL, GK_ENOMEM, GK_EDEVICE, GK_ENOREF, GK_ERANGE = 0, -1, -2, -3, -4, -5
+GK_REJECT, GK_ACCEPT, GK_UNDEFINED, GK_INVALID = 0, 1, 2, 3
+GK_EST_NONE = 0xFFFF
+GK_MAX_READ_LEN = 512
+STATUS_NAMES = {0: "GK_OK", -1: "GK_EINVAL", -2: "GK_ENOMEM", -3: "GK_EDEVICE",
+                -4: "GK_ENOREF", -5: "GK_ERANGE"}
+
+
+class GkError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class gk_batch(ctypes.Structure):
+    _fields_ = [
+        ("n_reads", ctypes.c_uint32),
+        ("pitch", ctypes.c_uint32),
+        ("max_read_len", ctypes.c_uint32),
+        ("e_uniform", ctypes.c_uint32),
+        ("reads", ctypes.c_void_p),
+        ("read_len", ctypes.c_void_p),
+        ("read_has_n", ctypes.c_void_p),
+        ("n_pairs", ctypes.c_uint64),
+        ("pair_read", ctypes.c_void_p),
+        ("cand_pos", ctypes.c_void_p),
+        ("e", ctypes.c_void_p),
+        ("accept", ctypes.c_void_p),
+        ("est", ctypes.c_void_p),
+        ("accept_bits", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libgk.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2103_14978_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        L.gk_create.argtypes = [i32, ctypes.POINTER(vp)]
+        L.gk_create.restype = i32
+        L.gk_destroy.argtypes = [vp]
+        L.gk_destroy.restype = None
+        L.gk_last_error.argtypes = [vp]
+        L.gk_last_error.restype = ctypes.c_char_p
+        L.gk_load_reference.argtypes = [vp, ctypes.c_char_p, u64]
+        L.gk_load_reference.restype = i32
+        L.gk_reference_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        L.gk_reference_info.restype = i32
+        L.gk_encode_reads.argtypes = [vp, vp, vp, u32, u32, u32, vp, vp, vp, vp]
+        L.gk_encode_reads.restype = i32
+        L.gk_filter.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
+        L.gk_filter.restype = i32
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
+            "gk_reference_info", "gk_encode_reads", "gk_filter")
+
+
+def ptr(x) -> int | None:
+    """Device address of a torch tensor, an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def stream_handle(s) -> int | None:
+    if s is None:
+        return None
+    if isinstance(s, int):
+        return s
+    return int(s.cuda_stream)
+
+
+def _check(ctx, status: int, what: str):
+    if status != GK_OK:
+        msg = lib().gk_last_error(ctx)
+        raise GkError(status, f"{what}: {msg.decode() if msg else ''}")
+
+
+def gk_create(device: int = 0) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    st = lib().gk_create(device, ctypes.byref(h))
+    _check(None, st, "gk_create")
+    return h
+
+
+def gk_destroy(ctx) -> None:
+    lib().gk_destroy(ctx)
+
+
+def gk_last_error(ctx) -> str:
+    m = lib().gk_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def gk_load_reference(ctx, ascii) -> None:
+    """ascii: bytes or a uint8 numpy array in host memory."""
+    if not isinstance(ascii, (bytes, bytearray)):
+        import numpy as np
+        a = np.ascontiguousarray(ascii, dtype=np.uint8)
+        buf = ctypes.cast(a.ctypes.data, ctypes.c_char_p)
+        n = a.size
+        st = lib().gk_load_reference(ctx, buf, n)
+    else:
+        st = lib().gk_load_reference(ctx, bytes(ascii), len(ascii))
+    _check(ctx, st, "gk_load_reference")
+
+
+def gk_reference_info(ctx) -> tuple[int, int]:
+    n, u = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(ctx, lib().gk_reference_info(ctx, ctypes.byref(n), ctypes.byref(u)),
+           "gk_reference_info")
+    return int(n.value), int(u.value)
+
+
+def gk_encode_reads(ctx, ascii, read_off, n_reads: int, pitch: int, rows: int, packed_out,
+                    len_out, has_n_out=None, stream=None) -> None:
+    st = lib().gk_encode_reads(ctx, ptr(ascii), ptr(read_off), n_reads, pitch, rows,
+                               ptr(packed_out), ptr(len_out), ptr(has_n_out),
+                               stream_handle(stream))
+    _check(ctx, st, "gk_encode_reads")
+
+
+def make_batch(*, n_reads, pitch, max_read_len, reads, read_len, pair_read, cand_pos, accept,
+               est, n_pairs=None, e=None, e_uniform=0, read_has_n=None,
+               accept_bits=None) -> gk_batch:
+    b = gk_batch()
+    b.n_reads = n_reads
+    b.pitch = pitch
+    b.max_read_len = max_read_len
+    b.e_uniform = e_uniform
+    b.reads = ptr(reads)
+    b.read_len = ptr(read_len)
+    b.read_has_n = ptr(read_has_n)
+    b.n_pairs = n_pairs if n_pairs is not None else int(cand_pos.numel())
+    b.pair_read = ptr(pair_read)
+    b.cand_pos = ptr(cand_pos)
+    b.e = ptr(e)
+    b.accept = ptr(accept)
+    b.est = ptr(est)
+    b.accept_bits = ptr(accept_bits)
+    return b
+
+
+def gk_filter(ctx, batch: gk_batch, stream=None) -> None:
+    _check(ctx, lib().gk_filter(ctx, ctypes.byref(batch), stream_handle(stream)), "gk_filter")

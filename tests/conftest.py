@@ -24,3 +24,16 @@ def golden_rows(name):
             if line and not line.startswith("#"):
                 rows.append(line.split())
     return rows
+
+
+@pytest.fixture(scope="session")
+def gkctx():
+    """A libgk context on cuda:0 (GPU tests only; fails loudly without a GPU)."""
+    import torch
+    from paper_2103_14978_amd import gk
+    if not torch.cuda.is_available():
+        raise RuntimeError("GPU test run without a visible GPU")
+    torch.cuda.init()
+    ctx = gk.gk_create(0)
+    yield ctx
+    gk.gk_destroy(ctx)
