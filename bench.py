@@ -78,6 +78,8 @@ def main() -> int:
     ap.add_argument("--e", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 256 MiB device copy kernel first (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the CPU-baseline sample")
     args = ap.parse_args()
@@ -119,6 +121,15 @@ def main() -> int:
     log("inputs resident")
 
     stream = torch.cuda.current_stream()
+    if args.calibrate_copy:
+        # An elementwise kernel reading 256 MiB and writing 256 MiB: the
+        # reference point that scales the FETCH_SIZE / WRITE_SIZE counters.
+        x = torch.ones(64 << 20, dtype=torch.int32, device=dev)
+        y = torch.empty_like(x)
+        torch.bitwise_xor(x, 0x55, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        log("copy calibration kernel: 268435456 bytes read, 268435456 bytes written")
     for _ in range(args.warmup):
         gk.gk_filter(ctx, batch, stream)
     torch.cuda.synchronize()
