@@ -76,6 +76,10 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--pairs", type=int, default=1 << 24)
     ap.add_argument("--e", type=int, default=5)
+    ap.add_argument("--layout", choices=["split", "interleaved"], default="split",
+                    help="2-bit read layout in HBM (both are 16 bases per 32-bit word)")
+    ap.add_argument("--pairs-per-lane", type=int, default=0,
+                    help="plain filter grid shape (0: one device residency)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -111,11 +115,17 @@ def main() -> int:
     log(f"generated reference + {ps.n_pairs} pairs in {time.time() - t:.1f}s")
 
     ctx = gk.gk_create(0)
+    gk.gk_set_option(ctx, gk.GK_OPT_PAIRS_PER_LANE, args.pairs_per_lane)
+    layout = gk.GK_READS_SPLIT if args.layout == "split" else gk.GK_READS_INTERLEAVED
     t = time.time()
     gk.gk_load_reference(ctx, ref)
     log(f"reference resident in {time.time() - t:.2f}s")
-    dr = device.encode_reads(ctx, ps.reads, ps.read_off, max_len=m)
-    dp = device.upload_pairs(ps.pair_read, ps.cand_pos, None, with_bits=False)
+    dr = device.encode_reads(ctx, ps.reads, ps.read_off, max_len=m, layout=layout)
+    # One candidate per read: pair i uses read i, which the batch states by
+    # leaving pair_read NULL.
+    identity = bool(np.array_equal(ps.pair_read, np.arange(n_pairs, dtype=np.uint32)))
+    dp = device.upload_pairs(None if identity else ps.pair_read, ps.cand_pos, None,
+                             with_bits=False)
     batch = device.batch_for(dr, dp, e_uniform=e, max_read_len=m)
     torch.cuda.synchronize()
     log("inputs resident")
@@ -204,8 +214,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"plain filter, {n_pairs} pairs of {m}bp reads, e={e}, "
                                "100 Mbp GC-41% reference, 30% true / 70% 12-mer decoys, "
-                               "reads 2-bit packed transposed",
-                   "pairs_per_step": n_pairs, "read_len": m, "e": e},
+                               "reads 2-bit packed transposed (16 bases per u32)",
+                   "pairs_per_step": n_pairs, "read_len": m, "e": e,
+                   "read_layout": args.layout, "pairs_per_lane": args.pairs_per_lane},
         "kernel_pairs_per_s": round(n_pairs / k_avg_s, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,

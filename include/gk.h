@@ -54,6 +54,12 @@ extern "C" {
                               index out of range                             */
 
 #define GK_EST_NONE      0xFFFFu  /* est of UNDEFINED / INVALID pairs        */
+
+/* Layouts of 2-bit encoded reads (A=00 C=01 G=10 T=11, Sec. 2.1): 16 bases
+   per 32-bit word, base i of a read in word i / 16 at j = i mod 16.        */
+#define GK_READS_SPLIT        0u  /* low code bit at bit j, high code bit at
+                                     bit 16 + j (the filter's native form)   */
+#define GK_READS_INTERLEAVED  1u  /* code at bits 2j (low) and 2j+1 (high)   */
 #define GK_MAX_READ_LEN  512u     /* longest read the kernels take           */
 #define GK_MAX_REF_LEN   0xFFFFFFFFull /* positions are 32-bit               */
 
@@ -91,18 +97,19 @@ int gk_reference_info(const gk_ctx *ctx, uint64_t *len, uint64_t *n_unknown);
  * ascii, read_off: DEVICE.  Read r is ascii[read_off[r] .. read_off[r+1]),
  * read_off has n_reads + 1 entries.
  * packed_out: DEVICE, rows * pitch words.  Word w of read r is written at
- * packed_out[w * pitch + r] (transposed, so a wavefront's loads coalesce):
- * base i of the read sits in bits 2(i mod 16), 2(i mod 16)+1 of word i / 16
- * (least-significant first); bits at or beyond twice the read length are 0,
- * words at or beyond ceil(len / 16) are 0.  Bases beyond 16 * rows are
- * dropped (give rows >= ceil(max length / 16)).
+ * packed_out[w * pitch + r] (transposed, so a wavefront's loads coalesce)
+ * and holds bases 16w .. 16w+15 in the given layout (GK_READS_*); code bits
+ * of positions at or beyond the read length are 0, words at or beyond
+ * ceil(len / 16) are 0.  Bases beyond 16 * rows are dropped (give rows >=
+ * ceil(max length / 16)).
  * len_out: DEVICE, n_reads entries: the read length (capped at 0xFFFF).
  * has_n_out: DEVICE, n_reads entries or NULL: 1 if the read holds a byte other
  * than A/C/G/T (either case) within its first 16 * rows bytes, else 0.
- * Requires pitch >= n_reads, 1 <= rows <= 32.  Asynchronous on stream.
+ * Requires n_reads < 2^30, pitch >= n_reads, pitch < 2^30, 1 <= rows <= 32,
+ * layout GK_READS_SPLIT or GK_READS_INTERLEAVED.  Asynchronous on stream.
  */
 int gk_encode_reads(gk_ctx *ctx, const uint8_t *ascii, const uint64_t *read_off,
-                    uint32_t n_reads, uint32_t pitch, uint32_t rows,
+                    uint32_t n_reads, uint32_t pitch, uint32_t rows, uint32_t layout,
                     uint32_t *packed_out, uint16_t *len_out, uint8_t *has_n_out,
                     void *stream);
 
@@ -120,13 +127,16 @@ typedef struct gk_batch {
                                       words per mask.  Reads longer than it
                                       give GK_INVALID pairs.                 */
     uint32_t        e_uniform;     /* threshold when e == NULL, 0..255       */
-    const uint32_t *reads;         /* packed 2-bit transposed, the layout
-                                      gk_encode_reads writes; needs
-                                      ceil(max_read_len/16) rows             */
+    uint32_t        read_layout;   /* GK_READS_SPLIT or GK_READS_INTERLEAVED */
+    const uint32_t *reads;         /* 2-bit encoded, 16 bases per word,
+                                      transposed as gk_encode_reads writes
+                                      them; ceil(max_read_len/16) rows of
+                                      pitch words                            */
     const uint16_t *read_len;      /* n_reads entries                        */
     const uint8_t  *read_has_n;    /* n_reads entries, or NULL (no unknowns) */
     uint64_t        n_pairs;
-    const uint32_t *pair_read;     /* n_pairs: read index of each pair       */
+    const uint32_t *pair_read;     /* n_pairs: read index of each pair, or
+                                      NULL: pair i uses read i              */
     const uint32_t *cand_pos;      /* n_pairs: 0-based window start          */
     const uint8_t  *e;             /* n_pairs thresholds, or NULL            */
     uint8_t        *accept;        /* out, n_pairs: GK_REJECT .. GK_INVALID  */
@@ -140,14 +150,84 @@ typedef struct gk_batch {
 } gk_batch;
 
 /*
- * Plain filter: one launch over all pairs of the batch, one GPU lane per pair
- * (Sec. 3.2: one thread per filtration), the read and window held as 32-base
- * bit-planes in registers.  Asynchronous on stream.
+ * Plain filter: one kernel launch over all pairs of the batch (one launch per
+ * 2^30 pairs), one GPU lane per pair at a time (Sec. 3.2: one thread per
+ * filtration), the read and window held as 32-base bit-planes in registers.
+ * Asynchronous on stream.
  * Errors (nothing launched): GK_EINVAL for NULL required pointers, pitch <
- * n_reads, max_read_len outside 1..512, e_uniform > 255; GK_ENOREF without a
- * reference; GK_ERANGE for n_pairs >= 2^38.
+ * n_reads, n_reads or pitch >= 2^30, max_read_len outside 1..512, e_uniform
+ * > 255, an unknown read_layout; GK_ENOREF without a reference; GK_ERANGE
+ * for n_pairs >= 2^38.
  */
 int gk_filter(gk_ctx *ctx, const gk_batch *batch, void *stream);
+
+/* Tuning options of a context (they never change results). */
+#define GK_OPT_PAIRS_PER_LANE 1   /* plain filter grid: 0 (default) =
+                                     automatic from e and the read length;
+                                     1 = one pair per lane; k in 2..65535 =
+                                     about k pairs per lane, each lane
+                                     keeping its next pair's loads in
+                                     flight; 65536 = one residency of the
+                                     device.  Range 0..65536.                */
+
+#define GK_OPT_MIXED_TILE           2  /* gk_filter_mixed: pairs per tile,
+                                            2048, 4096 (default) or 8192    */
+#define GK_OPT_MIXED_PAIRS_PER_LANE 3  /* gk_filter_mixed: 1 (default) or 2
+                                            pairs per lane per chunk        */
+#define GK_OPT_MIXED_SORT_E         4  /* gk_filter_mixed: 1 (default) sorts
+                                            a tile by (W, min(e, m-1)), 0 by
+                                            W only                          */
+#define GK_OPT_MIXED_BLOCKS_PER_CU  5  /* gk_filter_mixed: persistent
+                                            workgroups per CU, 0 (default) =
+                                            as many as fit, else 1..64      */
+#define GK_OPT_MIXED_GRAPH          6  /* gk_filter_mixed: 1 (default)
+                                            replays a captured hipGraph, 0
+                                            launches directly               */
+
+/* Set / get a tuning option.  GK_EINVAL for an unknown option or a value out
+   of range. */
+int gk_set_option(gk_ctx *ctx, int option, int64_t value);
+int gk_get_option(const gk_ctx *ctx, int option, int64_t *value);
+
+/*
+ * Mixed-batch filter: the same per-pair filter as gk_filter for batches whose
+ * pairs differ in read length and threshold (the paper compiles both in,
+ * Sec. 3.1, and would launch once per (length, e) group).
+ *
+ * One persistent launch covers the batch: workgroups claim tiles of
+ * consecutive pairs from a device counter, counting-sort each tile in LDS by
+ * (words per mask, min(e, m-1)) and run each 64-lane chunk through the fast
+ * path for its read length; pairs with more than 31 shifts are finished by a
+ * general-path pass; accept bits (if requested) by a pass over the accept
+ * codes.  The launch sequence is captured in a hipGraph the first time a
+ * given batch description and tuning are seen and replayed after that
+ * (GK_OPT_MIXED_GRAPH).  Results are identical to gk_filter's.
+ *
+ * Same batch rules and errors as gk_filter.  The context keeps scratch for
+ * it: two counters and a residual list of min(n_pairs, 2^30) entries (grown
+ * on demand, kept until gk_destroy).  Calls that overlap on one context race
+ * on that scratch: one gk_filter_mixed at a time per context.  Asynchronous
+ * on stream.
+ */
+int gk_filter_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream);
+
+/*
+ * Autotuner for gk_filter_mixed.  Times every candidate tuning (tile 2048 /
+ * 4096 / 8192, 1 or 2 pairs per lane, sort by e or not, full or half
+ * persistent grid) on the first sample_pairs pairs of the batch (0 = all),
+ * median of 3 runs each after a warm-up, and keeps the fastest in the
+ * context.  The outputs of the sampled pairs are written (correct results:
+ * every tuning gives the same ones).  Synchronous.
+ *
+ * cache_path (HOST string or NULL): a text file of JSON lines keyed by
+ * device architecture, CU count, words per mask, read layout, threshold mode
+ * and batch size (power-of-two bucket).  A matching line is used without
+ * timing anything; otherwise the measured choice is appended.
+ * report (HOST, report_cap bytes, or NULL): a JSON description of the
+ * choice and of every candidate's time, NUL-terminated, truncated to fit.
+ */
+int gk_tune_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream, uint64_t sample_pairs,
+                  const char *cache_path, char *report, size_t report_cap);
 
 #ifdef __cplusplus
 }

@@ -1,7 +1,11 @@
 // Host side of libgk: context, resident reference, argument checks, launches.
+#include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <new>
+#include <sstream>
 #include <string>
 
 #include "gk_internal.h"
@@ -83,6 +87,12 @@ int gk_create(int device, gk_ctx **out)
         g_create_error = "gk_create: hipSetDevice failed";
         return GK_EDEVICE;
     }
+    e = hipDeviceGetAttribute(&ctx->cu_count, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess || ctx->cu_count < 1) {
+        delete ctx;
+        g_create_error = "gk_create: cannot read the compute unit count";
+        return GK_EDEVICE;
+    }
     e = hipMalloc(&ctx->d_counter, sizeof(unsigned long long));
     if (e != hipSuccess) {
         delete ctx;
@@ -103,6 +113,14 @@ void gk_destroy(gk_ctx *ctx)
         free_reference(ctx);
         if (ctx->d_counter)
             (void)hipFree(ctx->d_counter);
+        if (ctx->graph_exec)
+            (void)hipGraphExecDestroy(ctx->graph_exec);
+        if (ctx->d_mixed_counters)
+            (void)hipFree(ctx->d_mixed_counters);
+        if (ctx->d_resid)
+            (void)hipFree(ctx->d_resid);
+        if (ctx->capture_stream)
+            (void)hipStreamDestroy(ctx->capture_stream);
     }
     delete ctx;
 }
@@ -184,8 +202,8 @@ int gk_reference_info(const gk_ctx *ctx, uint64_t *len, uint64_t *n_unknown)
 }
 
 int gk_encode_reads(gk_ctx *ctx, const uint8_t *ascii, const uint64_t *read_off, uint32_t n_reads,
-                    uint32_t pitch, uint32_t rows, uint32_t *packed_out, uint16_t *len_out,
-                    uint8_t *has_n_out, void *stream)
+                    uint32_t pitch, uint32_t rows, uint32_t layout, uint32_t *packed_out,
+                    uint16_t *len_out, uint8_t *has_n_out, void *stream)
 {
     if (!ctx)
         return GK_EINVAL;
@@ -195,45 +213,53 @@ int gk_encode_reads(gk_ctx *ctx, const uint8_t *ascii, const uint64_t *read_off,
         return fail(ctx, GK_EINVAL, "gk_encode_reads: NULL buffer");
     if (pitch < n_reads)
         return fail(ctx, GK_EINVAL, "gk_encode_reads: pitch < n_reads");
+    if (n_reads >= (1u << 30) || pitch >= (1u << 30))
+        return fail(ctx, GK_EINVAL, "gk_encode_reads: n_reads and pitch must be below 2^30");
     if (rows < 1 || rows > 32)
         return fail(ctx, GK_EINVAL, "gk_encode_reads: rows must be 1..32");
+    if (layout != GK_READS_SPLIT && layout != GK_READS_INTERLEAVED)
+        return fail(ctx, GK_EINVAL, "gk_encode_reads: unknown layout");
     DeviceGuard g(ctx->device);
     if (!g.ok)
         return fail(ctx, GK_EDEVICE, "gk_encode_reads: hipSetDevice failed");
-    hipError_t e = gkd::launch_encode_reads(ascii, read_off, n_reads, pitch, rows, packed_out,
-                                            len_out, has_n_out, (hipStream_t)stream);
+    hipError_t e = gkd::launch_encode_reads(ascii, read_off, n_reads, pitch, rows, layout,
+                                            packed_out, len_out, has_n_out, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "gk_encode_reads: launch");
     return GK_OK;
 }
 
-int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
-{
-    if (!ctx)
-        return GK_EINVAL;
-    if (!b)
-        return fail(ctx, GK_EINVAL, "gk_filter: batch is NULL");
-    if (!ctx->ref_planes)
-        return fail(ctx, GK_ENOREF, "gk_filter: no reference loaded");
-    if (b->max_read_len < 1 || b->max_read_len > GK_MAX_READ_LEN)
-        return fail(ctx, GK_EINVAL, "gk_filter: max_read_len must be 1..512");
-    if (b->e_uniform > 255)
-        return fail(ctx, GK_EINVAL, "gk_filter: e_uniform must be 0..255");
-    if (b->pitch < b->n_reads)
-        return fail(ctx, GK_EINVAL, "gk_filter: pitch < n_reads");
-    if (b->n_pairs == 0)
-        return GK_OK;
-    if (b->n_pairs >= (1ull << 38))
-        return fail(ctx, GK_ERANGE, "gk_filter: n_pairs must be below 2^38");
-    if (!b->pair_read || !b->cand_pos || !b->accept || !b->est)
-        return fail(ctx, GK_EINVAL, "gk_filter: NULL pair or output buffer");
-    if (b->n_reads > 0 && (!b->reads || !b->read_len))
-        return fail(ctx, GK_EINVAL, "gk_filter: NULL read buffer");
-    DeviceGuard g(ctx->device);
-    if (!g.ok)
-        return fail(ctx, GK_EDEVICE, "gk_filter: hipSetDevice failed");
+}  // extern "C"
 
-    gkd::FilterArgs a;
+namespace {
+
+// Checks a batch (nothing launched on failure) and fills the kernel
+// arguments.  Returns GK_OK, a GK_E* code, or 1 for an empty batch.
+int prepare_batch(gk_ctx *ctx, const gk_batch *b, const char *who, gkd::FilterArgs &a)
+{
+    const std::string w(who);
+    if (!b)
+        return fail(ctx, GK_EINVAL, w + ": batch is NULL");
+    if (!ctx->ref_planes)
+        return fail(ctx, GK_ENOREF, w + ": no reference loaded");
+    if (b->max_read_len < 1 || b->max_read_len > GK_MAX_READ_LEN)
+        return fail(ctx, GK_EINVAL, w + ": max_read_len must be 1..512");
+    if (b->e_uniform > 255)
+        return fail(ctx, GK_EINVAL, w + ": e_uniform must be 0..255");
+    if (b->pitch < b->n_reads)
+        return fail(ctx, GK_EINVAL, w + ": pitch < n_reads");
+    if (b->n_reads >= (1u << 30) || b->pitch >= (1u << 30))
+        return fail(ctx, GK_EINVAL, w + ": n_reads and pitch must be below 2^30");
+    if (b->read_layout != GK_READS_SPLIT && b->read_layout != GK_READS_INTERLEAVED)
+        return fail(ctx, GK_EINVAL, w + ": unknown read_layout");
+    if (b->n_pairs == 0)
+        return 1;
+    if (b->n_pairs >= (1ull << 38))
+        return fail(ctx, GK_ERANGE, w + ": n_pairs must be below 2^38");
+    if (!b->cand_pos || !b->accept || !b->est)
+        return fail(ctx, GK_EINVAL, w + ": NULL pair or output buffer");
+    if (b->n_reads > 0 && (!b->reads || !b->read_len))
+        return fail(ctx, GK_EINVAL, w + ": NULL read buffer");
     a.ref_planes = ctx->ref_planes;
     a.ref_unk = ctx->ref_unk;
     a.ref_len = ctx->ref_len;
@@ -242,6 +268,7 @@ int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
     a.pitch = b->pitch;
     a.e_uniform = b->e_uniform;
     a.max_read_len = b->max_read_len;
+    a.rows = (b->max_read_len + 15) / 16;
     a.reads = b->reads;
     a.read_len = b->read_len;
     a.read_has_n = b->read_has_n;
@@ -252,10 +279,365 @@ int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
     a.accept = b->accept;
     a.est = b->est;
     a.accept_bits = reinterpret_cast<unsigned long long *>(b->accept_bits);
+    return GK_OK;
+}
+
+void drop_graph(gk_ctx *ctx)
+{
+    if (ctx->graph_exec)
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+    ctx->graph_key.clear();
+}
+
+// Scratch for the mixed launch: counters and a residual list able to hold
+// every pair of one launch (at most 2^30).
+int ensure_mixed_scratch(gk_ctx *ctx, uint64_t n_pairs)
+{
+    hipError_t e;
+    if (!ctx->d_mixed_counters) {
+        e = hipMalloc(&ctx->d_mixed_counters, 2 * sizeof(uint32_t));
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_filter_mixed: hipMalloc counters");
+    }
+    const uint64_t need = n_pairs < (1ull << 30) ? n_pairs : (1ull << 30);
+    if (ctx->resid_cap < need) {
+        drop_graph(ctx);
+        if (ctx->d_resid)
+            (void)hipFree(ctx->d_resid);
+        ctx->d_resid = nullptr;
+        ctx->resid_cap = 0;
+        e = hipMalloc(&ctx->d_resid, need * sizeof(uint32_t));
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_filter_mixed: hipMalloc residual list");
+        ctx->resid_cap = need;
+    }
+    if (!ctx->capture_stream) {
+        e = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_filter_mixed: hipStreamCreate");
+    }
+    return GK_OK;
+}
+
+int mixed_args(gk_ctx *ctx, const MixedConfig &c, uint32_t wmax, uint32_t layout,
+               gkd::MixedArgs &x)
+{
+    int per_cu = 0;
+    hipError_t e = gkd::mixed_blocks_per_cu(wmax, layout, c.tile, c.ppl, &per_cu);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "gk_filter_mixed: occupancy");
+    if (per_cu < 1)
+        per_cu = 1;
+    const uint32_t bpc = c.blocks_per_cu && (int)c.blocks_per_cu < per_cu ? c.blocks_per_cu
+                                                                          : (uint32_t)per_cu;
+    x.tile_counter = ctx->d_mixed_counters;
+    x.resid_count = ctx->d_mixed_counters + 1;
+    x.resid_list = ctx->d_resid;
+    x.n_tiles = 0;
+    x.tile = c.tile;
+    x.ppl = c.ppl;
+    x.sort_e = c.sort_e;
+    x.blocks = bpc * (uint32_t)ctx->cu_count;
+    x.resid_blocks = 2u * (uint32_t)ctx->cu_count;
+    return GK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
+{
+    if (!ctx)
+        return GK_EINVAL;
+    gkd::FilterArgs a;
+    int st = prepare_batch(ctx, b, "gk_filter", a);
+    if (st != GK_OK)
+        return st == 1 ? GK_OK : st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok)
+        return fail(ctx, GK_EDEVICE, "gk_filter: hipSetDevice failed");
     const uint32_t words = (b->max_read_len + 31) / 32;
-    hipError_t e = gkd::launch_filter(a, words, (hipStream_t)stream);
+    hipError_t e = gkd::launch_filter(a, words, b->read_layout, ctx->pairs_per_lane,
+                                      (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "gk_filter: launch");
+    return GK_OK;
+}
+
+int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
+{
+    if (!ctx)
+        return GK_EINVAL;
+    gkd::FilterArgs a;
+    int st = prepare_batch(ctx, b, "gk_filter_mixed", a);
+    if (st != GK_OK)
+        return st == 1 ? GK_OK : st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok)
+        return fail(ctx, GK_EDEVICE, "gk_filter_mixed: hipSetDevice failed");
+    if ((st = ensure_mixed_scratch(ctx, b->n_pairs)) != GK_OK)
+        return st;
+    const uint32_t wmax = (b->max_read_len + 31) / 32;
+    gkd::MixedArgs x;
+    if ((st = mixed_args(ctx, ctx->mixed, wmax, b->read_layout, x)) != GK_OK)
+        return st;
+    hipError_t e;
+    if (!ctx->use_graph) {
+        e = gkd::launch_mixed(a, x, wmax, b->read_layout, (hipStream_t)stream);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_filter_mixed: launch");
+        return GK_OK;
+    }
+    // The launch sequence is captured once per distinct (arguments, tuning)
+    // and replayed from the graph afterwards.
+    std::vector<uint8_t> key(sizeof a + sizeof x + 8);
+    std::memcpy(key.data(), &a, sizeof a);
+    std::memcpy(key.data() + sizeof a, &x, sizeof x);
+    const uint32_t tail[2] = {wmax, b->read_layout};
+    std::memcpy(key.data() + sizeof a + sizeof x, tail, 8);
+    if (!ctx->graph_exec || key != ctx->graph_key) {
+        drop_graph(ctx);
+        hipGraph_t graph = nullptr;
+        e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_filter_mixed: begin capture");
+        hipError_t le = gkd::launch_mixed(a, x, wmax, b->read_layout, ctx->capture_stream);
+        e = hipStreamEndCapture(ctx->capture_stream, &graph);
+        if (le != hipSuccess || e != hipSuccess) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            return hip_fail(ctx, le != hipSuccess ? le : e, "gk_filter_mixed: capture");
+        }
+        e = hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            ctx->graph_exec = nullptr;
+            return hip_fail(ctx, e, "gk_filter_mixed: instantiate");
+        }
+        ctx->graph_key = key;
+    }
+    e = hipGraphLaunch(ctx->graph_exec, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "gk_filter_mixed: graph launch");
+    return GK_OK;
+}
+
+int gk_set_option(gk_ctx *ctx, int option, int64_t value)
+{
+    if (!ctx)
+        return GK_EINVAL;
+    switch (option) {
+    case GK_OPT_PAIRS_PER_LANE:
+        if (value < 0 || value > 65536)
+            return fail(ctx, GK_EINVAL, "gk_set_option: pairs per lane must be 0..65536");
+        ctx->pairs_per_lane = (uint32_t)value;
+        return GK_OK;
+    case GK_OPT_MIXED_TILE:
+        if (value != 2048 && value != 4096 && value != 8192)
+            return fail(ctx, GK_EINVAL, "gk_set_option: mixed tile must be 2048, 4096 or 8192");
+        ctx->mixed.tile = (uint32_t)value;
+        return GK_OK;
+    case GK_OPT_MIXED_PAIRS_PER_LANE:
+        if (value != 1 && value != 2)
+            return fail(ctx, GK_EINVAL, "gk_set_option: mixed pairs per lane must be 1 or 2");
+        ctx->mixed.ppl = (uint32_t)value;
+        return GK_OK;
+    case GK_OPT_MIXED_SORT_E:
+        if (value != 0 && value != 1)
+            return fail(ctx, GK_EINVAL, "gk_set_option: mixed sort-by-e must be 0 or 1");
+        ctx->mixed.sort_e = (uint32_t)value;
+        return GK_OK;
+    case GK_OPT_MIXED_BLOCKS_PER_CU:
+        if (value < 0 || value > 64)
+            return fail(ctx, GK_EINVAL, "gk_set_option: blocks per CU must be 0..64");
+        ctx->mixed.blocks_per_cu = (uint32_t)value;
+        return GK_OK;
+    case GK_OPT_MIXED_GRAPH:
+        if (value != 0 && value != 1)
+            return fail(ctx, GK_EINVAL, "gk_set_option: graph must be 0 or 1");
+        ctx->use_graph = (uint32_t)value;
+        return GK_OK;
+    default:
+        return fail(ctx, GK_EINVAL, "gk_set_option: unknown option");
+    }
+}
+
+int gk_get_option(const gk_ctx *ctx, int option, int64_t *value)
+{
+    if (!ctx || !value)
+        return GK_EINVAL;
+    switch (option) {
+    case GK_OPT_PAIRS_PER_LANE:
+        *value = ctx->pairs_per_lane;
+        return GK_OK;
+    case GK_OPT_MIXED_TILE:
+        *value = ctx->mixed.tile;
+        return GK_OK;
+    case GK_OPT_MIXED_PAIRS_PER_LANE:
+        *value = ctx->mixed.ppl;
+        return GK_OK;
+    case GK_OPT_MIXED_SORT_E:
+        *value = ctx->mixed.sort_e;
+        return GK_OK;
+    case GK_OPT_MIXED_BLOCKS_PER_CU:
+        *value = ctx->mixed.blocks_per_cu;
+        return GK_OK;
+    case GK_OPT_MIXED_GRAPH:
+        *value = ctx->use_graph;
+        return GK_OK;
+    default:
+        return GK_EINVAL;
+    }
+}
+
+int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_pairs,
+                  const char *cache_path, char *report, size_t report_cap)
+{
+    if (!ctx)
+        return GK_EINVAL;
+    gkd::FilterArgs a;
+    int st = prepare_batch(ctx, b, "gk_tune_mixed", a);
+    if (st != GK_OK)
+        return st == 1 ? GK_OK : st;
+    DeviceGuard g(ctx->device);
+    if (!g.ok)
+        return fail(ctx, GK_EDEVICE, "gk_tune_mixed: hipSetDevice failed");
+    if ((st = ensure_mixed_scratch(ctx, b->n_pairs)) != GK_OK)
+        return st;
+    const uint32_t wmax = (b->max_read_len + 31) / 32;
+    const uint64_t n_full = b->n_pairs;
+    if (sample_pairs && sample_pairs < a.n_pairs)
+        a.n_pairs = sample_pairs;
+    a.accept_bits = nullptr;
+
+    // Key: device, CU count, words per mask, layout, threshold mode, batch
+    // size (power-of-two bucket).
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess)
+        return fail(ctx, GK_EDEVICE, "gk_tune_mixed: device properties");
+    std::ostringstream k;
+    k << prop.gcnArchName << "|cu=" << ctx->cu_count << "|w=" << wmax
+      << "|layout=" << b->read_layout << "|e="
+      << (b->e ? std::string("per-pair") : "uniform:" + std::to_string(b->e_uniform))
+      << "|n=2^" << (int)std::floor(std::log2((double)n_full));
+    const std::string key = k.str();
+    std::ostringstream rep;
+
+    auto parse = [](const std::string &line, const char *field, long &out) {
+        const std::string f = std::string("\"") + field + "\": ";
+        const size_t p = line.find(f);
+        if (p == std::string::npos)
+            return false;
+        out = std::strtol(line.c_str() + p + f.size(), nullptr, 10);
+        return true;
+    };
+    if (cache_path && *cache_path) {
+        std::ifstream in(cache_path);
+        std::string line;
+        const std::string needle = "\"key\": \"" + key + "\"";
+        while (std::getline(in, line)) {
+            if (line.find(needle) == std::string::npos)
+                continue;
+            long t, p, se, bpc;
+            if (parse(line, "tile", t) && parse(line, "ppl", p) && parse(line, "sort_e", se) &&
+                parse(line, "blocks_per_cu", bpc) && (t == 2048 || t == 4096 || t == 8192) &&
+                (p == 1 || p == 2) && (se == 0 || se == 1) && bpc >= 0 && bpc <= 64) {
+                ctx->mixed = MixedConfig{(uint32_t)t, (uint32_t)p, (uint32_t)se, (uint32_t)bpc};
+                drop_graph(ctx);
+                rep << "{\"key\": \"" << key << "\", \"source\": \"cache\", \"tile\": " << t
+                    << ", \"ppl\": " << p << ", \"sort_e\": " << se << ", \"blocks_per_cu\": " << bpc
+                    << "}";
+                if (report && report_cap) {
+                    std::strncpy(report, rep.str().c_str(), report_cap - 1);
+                    report[report_cap - 1] = 0;
+                }
+                return GK_OK;
+            }
+        }
+    }
+
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(ctx, GK_EDEVICE, "gk_tune_mixed: hipEventCreate");
+    const hipStream_t s = (hipStream_t)stream;
+    int full_bpc = 0;
+    MixedConfig best;
+    float best_ms = -1.f;
+    rep << "{\"key\": \"" << key << "\", \"source\": \"measured\", \"sample_pairs\": " << a.n_pairs
+        << ", \"candidates\": [";
+    bool first = true;
+    hipError_t err = hipSuccess;
+    for (uint32_t tile : {2048u, 4096u, 8192u}) {
+        for (uint32_t ppl : {1u, 2u}) {
+            if (ppl == 2 && wmax > 10)
+                continue;                      // two pairs per lane only up to 10 words
+            if ((err = gkd::mixed_blocks_per_cu(wmax, b->read_layout, tile, ppl, &full_bpc)) !=
+                hipSuccess)
+                break;
+            for (uint32_t sort_e : {0u, 1u})
+                for (uint32_t bpc : {0u, (uint32_t)std::max(1, full_bpc / 2)}) {
+                    MixedConfig c{tile, ppl, sort_e, bpc};
+                    gkd::MixedArgs x;
+                    if ((st = mixed_args(ctx, c, wmax, b->read_layout, x)) != GK_OK) {
+                        (void)hipEventDestroy(e0);
+                        (void)hipEventDestroy(e1);
+                        return st;
+                    }
+                    float times[3];
+                    for (int rep_i = -1; rep_i < 3 && err == hipSuccess; ++rep_i) {
+                        err = hipEventRecord(e0, s);
+                        if (err == hipSuccess)
+                            err = gkd::launch_mixed(a, x, wmax, b->read_layout, s);
+                        if (err == hipSuccess)
+                            err = hipEventRecord(e1, s);
+                        if (err == hipSuccess)
+                            err = hipEventSynchronize(e1);
+                        float ms = 0;
+                        if (err == hipSuccess)
+                            err = hipEventElapsedTime(&ms, e0, e1);
+                        if (rep_i >= 0)
+                            times[rep_i] = ms;
+                    }
+                    if (err != hipSuccess)
+                        break;
+                    std::sort(times, times + 3);
+                    const float med = times[1];
+                    rep << (first ? "" : ", ") << "{\"tile\": " << tile << ", \"ppl\": " << ppl
+                        << ", \"sort_e\": " << sort_e << ", \"blocks_per_cu\": " << bpc
+                        << ", \"ms\": " << med << "}";
+                    first = false;
+                    if (best_ms < 0 || med < best_ms) {
+                        best_ms = med;
+                        best = c;
+                    }
+                }
+            if (err != hipSuccess)
+                break;
+        }
+        if (err != hipSuccess)
+            break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess)
+        return hip_fail(ctx, err, "gk_tune_mixed: timing");
+    ctx->mixed = best;
+    drop_graph(ctx);
+    rep << "], \"tile\": " << best.tile << ", \"ppl\": " << best.ppl << ", \"sort_e\": "
+        << best.sort_e << ", \"blocks_per_cu\": " << best.blocks_per_cu << ", \"ms\": " << best_ms
+        << "}";
+    if (cache_path && *cache_path) {
+        std::ofstream out(cache_path, std::ios::app);
+        out << "{\"key\": \"" << key << "\", \"tile\": " << best.tile << ", \"ppl\": " << best.ppl
+            << ", \"sort_e\": " << best.sort_e << ", \"blocks_per_cu\": " << best.blocks_per_cu
+            << ", \"ms\": " << best_ms << "}\n";
+    }
+    if (report && report_cap) {
+        std::strncpy(report, rep.str().c_str(), report_cap - 1);
+        report[report_cap - 1] = 0;
+    }
     return GK_OK;
 }
 

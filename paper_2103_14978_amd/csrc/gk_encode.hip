@@ -1,6 +1,7 @@
 // Encoding kernels (Sec. 3.3 and Sec. 3.5): ASCII -> 2-bit codes A=00 C=01
 // G=10 T=11 (Sec. 2.1), with every other byte recorded as an unknown base.
-//   k_encode_reads     reads -> 16 bases per 32-bit word, transposed rows
+//   k_encode_reads     reads -> 16 bases per 32-bit word (split or interleaved
+//                      code bits), transposed rows
 //   k_pack_reference   reference -> two bit-planes + unknown-base plane
 #include "gk_internal.h"
 
@@ -43,6 +44,7 @@ __device__ __forceinline__ void load16(const uint8_t *p, uint32_t n, uint32_t (&
     }
 }
 
+template <uint32_t LAYOUT>
 __global__ __launch_bounds__(256) void k_encode_reads(const uint8_t *ascii,
                                                       const uint64_t *read_off, uint32_t n_reads,
                                                       uint32_t pitch, uint32_t rows,
@@ -66,7 +68,11 @@ __global__ __launch_bounds__(256) void k_encode_reads(const uint8_t *ascii,
             for (int j = 0; j < 16; ++j) {
                 const uint32_t c = (b[j >> 2] >> (8 * (j & 3))) & 0xFFu;
                 if ((uint32_t)j < n) {
-                    word |= code_of(c) << (2 * j);
+                    const uint32_t code = code_of(c);
+                    if (LAYOUT == GK_READS_SPLIT)
+                        word |= ((code & 1u) << j) | ((code >> 1) << (16 + j));
+                    else
+                        word |= code << (2 * j);
                     unknown |= is_base(c) ? 0u : 1u;
                 }
             }
@@ -123,13 +129,19 @@ __global__ __launch_bounds__(256) void k_pack_reference(const uint8_t *ascii, ui
 }  // namespace
 
 hipError_t launch_encode_reads(const uint8_t *ascii, const uint64_t *read_off, uint32_t n_reads,
-                               uint32_t pitch, uint32_t rows, uint32_t *packed, uint16_t *len_out,
-                               uint8_t *has_n_out, hipStream_t s)
+                               uint32_t pitch, uint32_t rows, uint32_t layout, uint32_t *packed,
+                               uint16_t *len_out, uint8_t *has_n_out, hipStream_t s)
 {
     if (n_reads == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_encode_reads, dim3((n_reads + 255) / 256), dim3(256), 0, s, ascii,
-                       read_off, n_reads, pitch, rows, packed, len_out, has_n_out);
+    if (layout == GK_READS_SPLIT)
+        hipLaunchKernelGGL(k_encode_reads<GK_READS_SPLIT>, dim3((n_reads + 255) / 256), dim3(256),
+                           0, s, ascii, read_off, n_reads, pitch, rows, packed, len_out,
+                           has_n_out);
+    else
+        hipLaunchKernelGGL(k_encode_reads<GK_READS_INTERLEAVED>, dim3((n_reads + 255) / 256),
+                           dim3(256), 0, s, ascii, read_off, n_reads, pitch, rows, packed,
+                           len_out, has_n_out);
     return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "gk.h"
 
@@ -19,7 +20,17 @@
 namespace gkd {
 constexpr uint32_t REF_PAD_WORDS = 32;
 constexpr uint32_t MAX_WORDS = GK_MAX_READ_LEN / 32;  // 32-base words per mask
+constexpr uint32_t GK_PPL_RESIDENT = 65536;  // pairs-per-lane value meaning
+                                             // "one residency of the device"
 }  // namespace gkd
+
+// Tuning of the mixed-batch launch (never changes results).
+struct MixedConfig {
+    uint32_t tile = 4096;         // pairs per tile: 2048, 4096 or 8192
+    uint32_t ppl = 1;             // pairs per lane per chunk: 1 or 2
+    uint32_t sort_e = 1;          // sort a tile by (W, k_max) (1) or by W only (0)
+    uint32_t blocks_per_cu = 0;   // persistent grid: 0 = as many as fit
+};
 
 struct gk_ctx {
     int device = 0;
@@ -30,6 +41,17 @@ struct gk_ctx {
     uint2 *ref_planes = nullptr;
     uint32_t *ref_unk = nullptr;
     unsigned long long *d_counter = nullptr;  // scratch for the unknown count
+    uint32_t pairs_per_lane = 0;              // GK_OPT_PAIRS_PER_LANE
+    int cu_count = 0;
+    // mixed-batch launch
+    MixedConfig mixed;
+    uint32_t use_graph = 1;                   // GK_OPT_MIXED_GRAPH
+    uint32_t *d_mixed_counters = nullptr;     // [tile counter, residual count]
+    uint32_t *d_resid = nullptr;              // residual pair list
+    uint64_t resid_cap = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<uint8_t> graph_key;
 };
 
 namespace gkd {
@@ -44,6 +66,7 @@ struct FilterArgs {
     uint32_t e_uniform;
     uint32_t max_read_len;      // reads longer than this are GK_INVALID: the
                                 // read rows hold ceil(max_read_len/16) words
+    uint32_t rows;              // ceil(max_read_len / 16)
     const uint32_t *reads;
     const uint16_t *read_len;
     const uint8_t *read_has_n;
@@ -56,12 +79,33 @@ struct FilterArgs {
     unsigned long long *accept_bits;
 };
 
+struct MixedArgs {
+    uint32_t *tile_counter;      // zeroed by the launch sequence
+    uint32_t *resid_count;       // zeroed by the launch sequence
+    uint32_t *resid_list;        // capacity >= pairs per launch
+    uint32_t n_tiles;            // set per launch
+    uint32_t tile;               // pairs per tile (multiple of 256, <= 8192)
+    uint32_t ppl;                // 1 or 2
+    uint32_t sort_e;             // 0 or 1
+    uint32_t blocks;             // persistent workgroups
+    uint32_t resid_blocks;       // grid of the residual pass
+};
+
+// Mixed-batch launch sequence: reset, persistent kernel, residual pass and
+// (if a.accept_bits) the accept-bit pass, one set per 2^30 pairs.
+hipError_t launch_mixed(const FilterArgs &a, const MixedArgs &x, uint32_t wmax, uint32_t layout,
+                        hipStream_t s);
+hipError_t mixed_blocks_per_cu(uint32_t wmax, uint32_t layout, uint32_t tile, uint32_t ppl,
+                               int *out);
+size_t mixed_lds_size(uint32_t tile);
+
 // Launch the plain filter with `words` 32-base words per mask (1..16).
-hipError_t launch_filter(const FilterArgs &a, uint32_t words, hipStream_t s);
+hipError_t launch_filter(const FilterArgs &a, uint32_t words, uint32_t layout,
+                         uint32_t pairs_per_lane, hipStream_t s);
 
 hipError_t launch_encode_reads(const uint8_t *ascii, const uint64_t *read_off, uint32_t n_reads,
-                               uint32_t pitch, uint32_t rows, uint32_t *packed, uint16_t *len_out,
-                               uint8_t *has_n_out, hipStream_t s);
+                               uint32_t pitch, uint32_t rows, uint32_t layout, uint32_t *packed,
+                               uint16_t *len_out, uint8_t *has_n_out, hipStream_t s);
 
 // Pack bases [first, first + n) of the reference, first a multiple of 32,
 // from the device staging buffer `ascii` (holding those n bytes) into the

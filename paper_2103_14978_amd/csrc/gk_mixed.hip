@@ -1,0 +1,382 @@
+// Mixed-batch GateKeeper-GPU filter for gfx950: one persistent launch over a
+// batch whose pairs differ in read length and threshold.
+//
+// The paper fixes the read length and e at compile time (Sec. 3.1, 3.2) and
+// so runs one kernel per (length, e) group.  Here one persistent grid takes
+// the whole batch:
+//   - each workgroup repeatedly claims a tile of T consecutive pairs from a
+//     device counter;
+//   - it classifies the tile's pairs (invalid and undefined pairs are written
+//     at once, pairs with more than 31 shifts go to a residual list) and
+//     counting-sorts the rest in LDS by (words per mask W, k_max), so that a
+//     64-lane chunk holds one W and nearly equal e;
+//   - its waves take chunks from an LDS counter and run the register-only
+//     fast path of gk_pair.h for the chunk's W (a wave-uniform switch), one
+//     or two pairs per lane (two: both pairs' loads in flight before either
+//     is computed; only for up to 10 words per mask, where the registers for
+//     it fit); results go back to the pairs' own slots.
+// Residual pairs are filtered afterwards by the general path, and the accept
+// bits (if wanted) by a pass over the accept codes.  The host captures the
+// four launches in one hipGraph.
+#include "gk_pair.h"
+
+namespace gkd {
+
+namespace {
+
+constexpr uint32_t NBINS = 16 * 32;       // W in 1..16, k_max in 0..31
+constexpr uint32_t KEY_DONE = 0xFFFFu;
+
+struct MixedLds {
+    uint32_t hist[NBINS];
+    uint32_t wstart[17];
+    uint32_t tile;
+    uint32_t n_chunks;
+    uint32_t next_chunk;
+};
+
+// Dynamic LDS after MixedLds: keys[T] u16, sorted[T] u16, chunk_start[C] u32,
+// chunk_info[C] u32 with C = T/64 + 16.
+__host__ __device__ inline uint32_t mixed_chunk_cap(uint32_t tile) { return tile / 64 + 16; }
+
+__host__ inline size_t mixed_lds_bytes(uint32_t tile)
+{
+    return sizeof(MixedLds) + 2u * tile * sizeof(uint16_t) + 2u * mixed_chunk_cap(tile) * 4u;
+}
+
+template <int W, int L>
+__device__ __forceinline__ void run_chunk_pair(const FilterArgs &a, uint32_t i)
+{
+    const PairIdx p = load_idx(a, i);
+    PairData<W> d;
+    load_data<W>(a, p, d);
+    uint32_t est;
+    const uint32_t res = compute_pair<W, L, false>(a, p, d, est);
+    __builtin_nontemporal_store((uint8_t)res, a.accept + i);
+    __builtin_nontemporal_store((uint16_t)est, a.est + i);
+}
+
+template <int W, int L>
+__device__ __forceinline__ void run_chunk_pair2(const FilterArgs &a, uint32_t i0, bool has1,
+                                                uint32_t i1)
+{
+    // both pairs' loads in flight before either is computed
+    const PairIdx p0 = load_idx(a, i0);
+    const PairIdx p1 = load_idx(a, has1 ? i1 : i0);
+    PairData<W> d0, d1;
+    load_data<W>(a, p0, d0);
+    load_data<W>(a, p1, d1);
+    uint32_t est;
+    uint32_t res = compute_pair<W, L, false>(a, p0, d0, est);
+    __builtin_nontemporal_store((uint8_t)res, a.accept + i0);
+    __builtin_nontemporal_store((uint16_t)est, a.est + i0);
+    if (has1) {
+        res = compute_pair<W, L, false>(a, p1, d1, est);
+        __builtin_nontemporal_store((uint8_t)res, a.accept + i1);
+        __builtin_nontemporal_store((uint16_t)est, a.est + i1);
+    }
+}
+
+template <int WMAX, int L, int PPL>
+__device__ __forceinline__ void run_chunk(const FilterArgs &a, uint32_t w, uint32_t i0, bool has1,
+                                          uint32_t i1)
+{
+#define GK_CASE(N)                                                        \
+    case N:                                                               \
+        if (N <= WMAX) {                                                  \
+            if (PPL == 2)                                                 \
+                run_chunk_pair2<(N <= WMAX ? N : 1), L>(a, i0, has1, i1); \
+            else                                                          \
+                run_chunk_pair<(N <= WMAX ? N : 1), L>(a, i0);            \
+        }                                                                 \
+        break;
+    switch (w) {
+        GK_CASE(1) GK_CASE(2) GK_CASE(3) GK_CASE(4) GK_CASE(5) GK_CASE(6) GK_CASE(7) GK_CASE(8)
+        GK_CASE(9) GK_CASE(10) GK_CASE(11) GK_CASE(12) GK_CASE(13) GK_CASE(14) GK_CASE(15)
+        GK_CASE(16)
+    default:
+        break;
+    }
+#undef GK_CASE
+}
+
+template <int WMAX, int L, int PPL>
+__global__ __launch_bounds__(256) void k_mixed(FilterArgs a, MixedArgs x)
+{
+    extern __shared__ uint32_t lds_raw[];
+    MixedLds &s = *reinterpret_cast<MixedLds *>(lds_raw);
+    uint16_t *keys = reinterpret_cast<uint16_t *>(lds_raw + sizeof(MixedLds) / 4);
+    uint16_t *sorted = keys + x.tile;
+    uint32_t *chunk_start = reinterpret_cast<uint32_t *>(sorted + x.tile);
+    uint32_t *chunk_info = chunk_start + mixed_chunk_cap(x.tile);
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63u;
+    const uint32_t n = (uint32_t)a.n_pairs;
+
+    while (true) {
+        if (tid == 0)
+            s.tile = atomicAdd(x.tile_counter, 1u);
+        for (uint32_t b = tid; b < NBINS; b += 256)
+            s.hist[b] = 0;
+        __syncthreads();
+        const uint32_t tile = s.tile;
+        if (tile >= x.n_tiles)
+            break;
+        const uint32_t base = tile * x.tile;
+
+        // 1. classify
+        for (uint32_t j = tid; j < x.tile; j += 256) {
+            const uint32_t i = base + j;
+            uint32_t key = KEY_DONE;
+            if (i < n) {
+                const PairIdx p = load_idx(a, i);
+                const uint32_t m = p.r < a.n_reads ? (uint32_t)a.read_len[p.r] : 0u;
+                if (m == 0u || m > a.max_read_len) {
+                    a.accept[i] = GK_INVALID;
+                    a.est[i] = GK_EST_NONE;
+                } else if ((uint64_t)p.pos + m > a.ref_len ||
+                           (a.read_has_n && a.read_has_n[p.r])) {
+                    a.accept[i] = GK_UNDEFINED;
+                    a.est[i] = GK_EST_NONE;
+                } else {
+                    const uint32_t kmax = p.e < m - 1u ? p.e : m - 1u;
+                    const uint32_t w = (m + 31u) / 32u;
+                    if (kmax > 31u || w > (uint32_t)WMAX) {
+                        x.resid_list[atomicAdd(x.resid_count, 1u)] = i;
+                    } else {
+                        key = (w - 1u) * 32u + (x.sort_e ? kmax : 0u);
+                        atomicAdd(&s.hist[key], 1u);
+                    }
+                }
+            }
+            keys[j] = (uint16_t)key;
+        }
+        __syncthreads();
+
+        // 2. exclusive prefix over the bins (wave 0: 8 bins per lane)
+        if (tid < 64) {
+            uint32_t local[8], sum = 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                local[q] = s.hist[tid * 8 + q];
+                sum += local[q];
+            }
+            uint32_t incl = sum;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t v = __shfl_up(incl, o, 64);
+                if (lane >= (uint32_t)o)
+                    incl += v;
+            }
+            uint32_t run = incl - sum;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t b = tid * 8 + q;
+                if (b % 32u == 0u)
+                    s.wstart[b / 32u] = run;
+                s.hist[b] = run;
+                run += local[q];
+            }
+            if (tid == 63)
+                s.wstart[16] = run;
+        }
+        __syncthreads();
+
+        // 3. scatter slots into bin order
+        for (uint32_t j = tid; j < x.tile; j += 256) {
+            const uint32_t key = keys[j];
+            if (key != KEY_DONE)
+                sorted[atomicAdd(&s.hist[key], 1u)] = (uint16_t)j;
+        }
+
+        // 4. chunks: runs of one W, 64 * ppl pairs at most
+        if (tid < 64) {
+            const uint32_t ch = 64u * PPL;
+            const uint32_t w0 = tid < 16 ? s.wstart[tid] : 0u;
+            const uint32_t cnt = tid < 16 ? s.wstart[tid + 1] - w0 : 0u;
+            const uint32_t nch = (cnt + ch - 1) / ch;
+            uint32_t incl = nch;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t v = __shfl_up(incl, o, 64);
+                if (lane >= (uint32_t)o)
+                    incl += v;
+            }
+            const uint32_t first = incl - nch;
+            for (uint32_t c = 0; c < nch; ++c) {
+                chunk_start[first + c] = w0 + c * ch;
+                const uint32_t left = cnt - c * ch;
+                chunk_info[first + c] = (left < ch ? left : ch) | ((tid + 1u) << 16);
+            }
+            if (tid == 63) {
+                s.n_chunks = incl;
+                s.next_chunk = 0;
+            }
+        }
+        __syncthreads();
+
+        // 5. waves take chunks
+        const uint32_t n_chunks = s.n_chunks;
+        while (true) {
+            uint32_t c = 0;
+            if (lane == 0)
+                c = atomicAdd(&s.next_chunk, 1u);
+            c = __shfl(c, 0, 64);
+            if (c >= n_chunks)
+                break;
+            const uint32_t start = chunk_start[c];
+            const uint32_t info = chunk_info[c];
+            const uint32_t cnt = info & 0xFFFFu;
+            const uint32_t w = __builtin_amdgcn_readfirstlane(info >> 16);
+            if (lane < cnt) {
+                const uint32_t i0 = base + sorted[start + lane];
+                const bool has1 = lane + 64u < cnt;
+                const uint32_t i1 = has1 ? base + sorted[start + lane + 64u] : i0;
+                run_chunk<WMAX, L, PPL>(a, w, i0, has1, i1);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int W, int L>
+__global__ __launch_bounds__(256) void k_residual(FilterArgs a, const uint32_t *list,
+                                                  const uint32_t *count)
+{
+    const uint32_t total = *count;
+    for (uint32_t j = blockIdx.x * 256u + threadIdx.x; j < total; j += gridDim.x * 256u) {
+        const uint32_t i = list[j];
+        const PairIdx p = load_idx(a, i);
+        PairData<W> d;
+        load_data<W>(a, p, d);
+        uint32_t est;
+        const uint32_t res = compute_pair<W, L, true>(a, p, d, est);
+        a.accept[i] = (uint8_t)res;
+        a.est[i] = (uint16_t)est;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_reset(uint32_t *tile_counter, uint32_t *resid_count)
+{
+    if (threadIdx.x == 0) {
+        *tile_counter = 0;
+        *resid_count = 0;
+    }
+}
+
+// One thread per 64 pairs: bit j of word t = pair 64t+j is ACCEPT or UNDEFINED.
+__global__ __launch_bounds__(256) void k_accept_bits(const uint8_t *accept, uint64_t n,
+                                                     unsigned long long *bits)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    if (t * 64 >= n)
+        return;
+    unsigned long long word = 0;
+    const uint64_t first = t * 64;
+    const uint32_t cnt = (uint32_t)(n - first < 64 ? n - first : 64);
+    for (uint32_t j = 0; j < cnt; ++j) {
+        const uint32_t v = accept[first + j];
+        word |= (unsigned long long)(v == GK_ACCEPT || v == GK_UNDEFINED) << j;
+    }
+    bits[t] = word;
+}
+
+template <int WMAX, int L>
+hipError_t launch_mixed_wl(const FilterArgs &a, const MixedArgs &x0, hipStream_t s)
+{
+    const uint64_t CHUNK = 1ull << 30;
+    for (uint64_t first = 0; first < a.n_pairs; first += CHUNK) {
+        FilterArgs c = a;
+        const uint64_t n = a.n_pairs - first < CHUNK ? a.n_pairs - first : CHUNK;
+        c.n_pairs = n;
+        c.pair_read = a.pair_read ? a.pair_read + first : nullptr;
+        c.cand_pos = a.cand_pos + first;
+        c.e_pair = a.e_pair ? a.e_pair + first : nullptr;
+        c.accept = a.accept + first;
+        c.est = a.est + first;
+        c.accept_bits = nullptr;
+        MixedArgs x = x0;
+        x.n_tiles = (uint32_t)((n + x.tile - 1) / x.tile);
+        hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, x.tile_counter, x.resid_count);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        const uint32_t blocks = x.blocks < x.n_tiles ? x.blocks : x.n_tiles;
+        if constexpr (WMAX <= 10) {
+            if (x.ppl == 2)
+                hipLaunchKernelGGL((k_mixed<WMAX, L, 2>), dim3(blocks), dim3(256),
+                                   mixed_lds_bytes(x.tile), s, c, x);
+            else
+                hipLaunchKernelGGL((k_mixed<WMAX, L, 1>), dim3(blocks), dim3(256),
+                                   mixed_lds_bytes(x.tile), s, c, x);
+        } else {
+            hipLaunchKernelGGL((k_mixed<WMAX, L, 1>), dim3(blocks), dim3(256),
+                               mixed_lds_bytes(x.tile), s, c, x);
+        }
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        hipLaunchKernelGGL((k_residual<WMAX, L>), dim3(x.resid_blocks), dim3(256), 0, s, c,
+                           (const uint32_t *)x.resid_list, (const uint32_t *)x.resid_count);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return e;
+        if (a.accept_bits) {
+            const uint64_t words = (n + 63) / 64;
+            hipLaunchKernelGGL(k_accept_bits, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0,
+                               s, (const uint8_t *)c.accept, n, a.accept_bits + first / 64);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return e;
+        }
+    }
+    return hipSuccess;
+}
+
+template <int L>
+hipError_t launch_mixed_l(const FilterArgs &a, const MixedArgs &x, uint32_t wmax, hipStream_t s)
+{
+    if (wmax <= 4)
+        return launch_mixed_wl<4, L>(a, x, s);
+    if (wmax <= 10)
+        return launch_mixed_wl<10, L>(a, x, s);
+    return launch_mixed_wl<16, L>(a, x, s);
+}
+
+template <int WMAX, int L>
+hipError_t occupancy_wl(uint32_t tile, uint32_t ppl, int *blocks_per_cu)
+{
+    if constexpr (WMAX <= 10) {
+        if (ppl == 2)
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                blocks_per_cu, k_mixed<WMAX, L, 2>, 256, mixed_lds_bytes(tile));
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_mixed<WMAX, L, 1>, 256,
+                                                        mixed_lds_bytes(tile));
+}
+
+}  // namespace
+
+size_t mixed_lds_size(uint32_t tile) { return mixed_lds_bytes(tile); }
+
+hipError_t mixed_blocks_per_cu(uint32_t wmax, uint32_t layout, uint32_t tile, uint32_t ppl,
+                               int *out)
+{
+    const bool il = layout == GK_READS_INTERLEAVED;
+    if (wmax <= 4)
+        return il ? occupancy_wl<4, GK_READS_INTERLEAVED>(tile, ppl, out)
+                  : occupancy_wl<4, GK_READS_SPLIT>(tile, ppl, out);
+    if (wmax <= 10)
+        return il ? occupancy_wl<10, GK_READS_INTERLEAVED>(tile, ppl, out)
+                  : occupancy_wl<10, GK_READS_SPLIT>(tile, ppl, out);
+    return il ? occupancy_wl<16, GK_READS_INTERLEAVED>(tile, ppl, out)
+              : occupancy_wl<16, GK_READS_SPLIT>(tile, ppl, out);
+}
+
+hipError_t launch_mixed(const FilterArgs &a, const MixedArgs &x, uint32_t wmax, uint32_t layout,
+                        hipStream_t s)
+{
+    return layout == GK_READS_INTERLEAVED
+               ? launch_mixed_l<GK_READS_INTERLEAVED>(a, x, wmax, s)
+               : launch_mixed_l<GK_READS_SPLIT>(a, x, wmax, s);
+}
+
+}  // namespace gkd

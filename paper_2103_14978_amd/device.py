@@ -31,13 +31,15 @@ class DeviceReads:
     n_reads: int
     pitch: int
     max_len: int
+    layout: int                 # gk.GK_READS_*
     packed: torch.Tensor        # uint32 [rows * pitch] (int32 storage)
     read_len: torch.Tensor      # uint16 (int16 storage)
     has_n: torch.Tensor         # uint8
 
 
 def encode_reads(ctx, reads_ascii: np.ndarray, read_off: np.ndarray, *, max_len: int | None = None,
-                 device="cuda", stream=None, pitch_align: int = 64) -> DeviceReads:
+                 device="cuda", stream=None, pitch_align: int = 64,
+                 layout: int = gk.GK_READS_SPLIT) -> DeviceReads:
     """Upload ASCII reads and encode them on the GPU (gk_encode_reads)."""
     read_off = np.ascontiguousarray(read_off, dtype=np.uint64)
     n = len(read_off) - 1
@@ -53,16 +55,16 @@ def encode_reads(ctx, reads_ascii: np.ndarray, read_off: np.ndarray, *, max_len:
     packed = torch.empty(rows * pitch, dtype=torch.int32, device=device)
     rl = torch.empty(max(n, 1), dtype=torch.int16, device=device)
     hn = torch.empty(max(n, 1), dtype=torch.uint8, device=device)
-    gk.gk_encode_reads(ctx, ascii_d, off_d, n, pitch, rows, packed, rl, hn, stream)
+    gk.gk_encode_reads(ctx, ascii_d, off_d, n, pitch, rows, layout, packed, rl, hn, stream)
     torch.cuda.synchronize()
     del ascii_d, off_d
-    return DeviceReads(n, pitch, max_len, packed, rl, hn)
+    return DeviceReads(n, pitch, max_len, layout, packed, rl, hn)
 
 
 @dataclass
 class DevicePairs:
     n_pairs: int
-    pair_read: torch.Tensor     # uint32 (int32 storage)
+    pair_read: torch.Tensor | None  # uint32 (int32 storage); None = identity
     cand_pos: torch.Tensor      # uint32 (int32 storage)
     e: torch.Tensor | None      # uint8
     accept: torch.Tensor        # uint8
@@ -70,10 +72,12 @@ class DevicePairs:
     accept_bits: torch.Tensor | None  # uint64 (int64 storage)
 
 
-def upload_pairs(pair_read: np.ndarray, cand_pos: np.ndarray, e: np.ndarray | None = None, *,
-                 device="cuda", with_bits: bool = False) -> DevicePairs:
+def upload_pairs(pair_read: np.ndarray | None, cand_pos: np.ndarray, e: np.ndarray | None = None,
+                 *, device="cuda", with_bits: bool = False) -> DevicePairs:
+    """pair_read None: pair i uses read i (one candidate per read)."""
     n = len(cand_pos)
-    pr = _dev(np.ascontiguousarray(pair_read, dtype=np.uint32).view(np.int32), device)
+    pr = (_dev(np.ascontiguousarray(pair_read, dtype=np.uint32).view(np.int32), device)
+          if pair_read is not None else None)
     cp = _dev(np.ascontiguousarray(cand_pos, dtype=np.uint32).view(np.int32), device)
     ed = _dev(np.ascontiguousarray(e, dtype=np.uint8), device) if e is not None else None
     acc = torch.empty(max(n, 1), dtype=torch.uint8, device=device)
@@ -90,7 +94,7 @@ def batch_for(reads: DeviceReads, pairs: DevicePairs, *, e_uniform: int = 0,
         reads=reads.packed, read_len=reads.read_len, read_has_n=reads.has_n,
         n_pairs=pairs.n_pairs, pair_read=pairs.pair_read, cand_pos=pairs.cand_pos,
         e=pairs.e, e_uniform=e_uniform, accept=pairs.accept, est=pairs.est,
-        accept_bits=pairs.accept_bits)
+        accept_bits=pairs.accept_bits, read_layout=reads.layout)
 
 
 def results(pairs: DevicePairs) -> tuple[np.ndarray, np.ndarray]:

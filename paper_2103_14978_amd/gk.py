@@ -19,6 +19,13 @@ GK_OK, GK_EINVAL, GK_ENOMEM, GK_EDEVICE, GK_ENOREF, GK_ERANGE = 0, -1, -2, -3, -
 GK_REJECT, GK_ACCEPT, GK_UNDEFINED, GK_INVALID = 0, 1, 2, 3
 GK_EST_NONE = 0xFFFF
 GK_MAX_READ_LEN = 512
+GK_READS_SPLIT, GK_READS_INTERLEAVED = 0, 1
+GK_OPT_PAIRS_PER_LANE = 1
+GK_OPT_MIXED_TILE = 2
+GK_OPT_MIXED_PAIRS_PER_LANE = 3
+GK_OPT_MIXED_SORT_E = 4
+GK_OPT_MIXED_BLOCKS_PER_CU = 5
+GK_OPT_MIXED_GRAPH = 6
 STATUS_NAMES = {0: "GK_OK", -1: "GK_EINVAL", -2: "GK_ENOMEM", -3: "GK_EDEVICE",
                 -4: "GK_ENOREF", -5: "GK_ERANGE"}
 
@@ -35,6 +42,7 @@ class gk_batch(ctypes.Structure):
         ("pitch", ctypes.c_uint32),
         ("max_read_len", ctypes.c_uint32),
         ("e_uniform", ctypes.c_uint32),
+        ("read_layout", ctypes.c_uint32),
         ("reads", ctypes.c_void_p),
         ("read_len", ctypes.c_void_p),
         ("read_has_n", ctypes.c_void_p),
@@ -70,16 +78,26 @@ def lib() -> ctypes.CDLL:
         L.gk_load_reference.restype = i32
         L.gk_reference_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.gk_reference_info.restype = i32
-        L.gk_encode_reads.argtypes = [vp, vp, vp, u32, u32, u32, vp, vp, vp, vp]
+        L.gk_encode_reads.argtypes = [vp, vp, vp, u32, u32, u32, u32, vp, vp, vp, vp]
         L.gk_encode_reads.restype = i32
         L.gk_filter.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
         L.gk_filter.restype = i32
+        L.gk_filter_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
+        L.gk_filter_mixed.restype = i32
+        L.gk_tune_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp, u64, ctypes.c_char_p,
+                                    ctypes.c_char_p, ctypes.c_size_t]
+        L.gk_tune_mixed.restype = i32
+        L.gk_set_option.argtypes = [vp, i32, ctypes.c_int64]
+        L.gk_set_option.restype = i32
+        L.gk_get_option.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
+        L.gk_get_option.restype = i32
         _lib = L
     return _lib
 
 
 EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
-            "gk_reference_info", "gk_encode_reads", "gk_filter")
+            "gk_reference_info", "gk_encode_reads", "gk_filter", "gk_set_option",
+            "gk_get_option", "gk_filter_mixed", "gk_tune_mixed")
 
 
 def ptr(x) -> int | None:
@@ -141,22 +159,33 @@ def gk_reference_info(ctx) -> tuple[int, int]:
     return int(n.value), int(u.value)
 
 
-def gk_encode_reads(ctx, ascii, read_off, n_reads: int, pitch: int, rows: int, packed_out,
-                    len_out, has_n_out=None, stream=None) -> None:
-    st = lib().gk_encode_reads(ctx, ptr(ascii), ptr(read_off), n_reads, pitch, rows,
+def gk_encode_reads(ctx, ascii, read_off, n_reads: int, pitch: int, rows: int, layout: int,
+                    packed_out, len_out, has_n_out=None, stream=None) -> None:
+    st = lib().gk_encode_reads(ctx, ptr(ascii), ptr(read_off), n_reads, pitch, rows, layout,
                                ptr(packed_out), ptr(len_out), ptr(has_n_out),
                                stream_handle(stream))
     _check(ctx, st, "gk_encode_reads")
 
 
+def gk_set_option(ctx, option: int, value: int) -> None:
+    _check(ctx, lib().gk_set_option(ctx, option, value), "gk_set_option")
+
+
+def gk_get_option(ctx, option: int) -> int:
+    v = ctypes.c_int64()
+    _check(ctx, lib().gk_get_option(ctx, option, ctypes.byref(v)), "gk_get_option")
+    return int(v.value)
+
+
 def make_batch(*, n_reads, pitch, max_read_len, reads, read_len, pair_read, cand_pos, accept,
-               est, n_pairs=None, e=None, e_uniform=0, read_has_n=None,
-               accept_bits=None) -> gk_batch:
+               est, n_pairs=None, e=None, e_uniform=0, read_has_n=None, accept_bits=None,
+               read_layout=GK_READS_SPLIT) -> gk_batch:
     b = gk_batch()
     b.n_reads = n_reads
     b.pitch = pitch
     b.max_read_len = max_read_len
     b.e_uniform = e_uniform
+    b.read_layout = read_layout
     b.reads = ptr(reads)
     b.read_len = ptr(read_len)
     b.read_has_n = ptr(read_has_n)
@@ -172,3 +201,18 @@ def make_batch(*, n_reads, pitch, max_read_len, reads, read_len, pair_read, cand
 
 def gk_filter(ctx, batch: gk_batch, stream=None) -> None:
     _check(ctx, lib().gk_filter(ctx, ctypes.byref(batch), stream_handle(stream)), "gk_filter")
+
+
+def gk_filter_mixed(ctx, batch: gk_batch, stream=None) -> None:
+    _check(ctx, lib().gk_filter_mixed(ctx, ctypes.byref(batch), stream_handle(stream)),
+           "gk_filter_mixed")
+
+
+def gk_tune_mixed(ctx, batch: gk_batch, stream=None, sample_pairs: int = 0,
+                  cache_path: str | None = None, report_cap: int = 1 << 16) -> str:
+    """Returns the tuner's JSON report."""
+    buf = ctypes.create_string_buffer(report_cap)
+    st = lib().gk_tune_mixed(ctx, ctypes.byref(batch), stream_handle(stream), sample_pairs,
+                             cache_path.encode() if cache_path else None, buf, report_cap)
+    _check(ctx, st, "gk_tune_mixed")
+    return buf.value.decode()

@@ -17,11 +17,18 @@ def say(msg: str):
 
 
 def run_gpu(ctx, ref_loaded_ascii, reads, read_off, pair_read, cand_pos, e, *, max_read_len=None,
-            with_bits=False, load_ref=True):
-    """Filter on the GPU.  e is an int (uniform) or a uint8 array per pair."""
+            with_bits=False, load_ref=True, layout=gk.GK_READS_SPLIT, pairs_per_lane=None,
+            identity_as_null=False):
+    """Filter on the GPU.  e is an int (uniform) or a uint8 array per pair.
+    identity_as_null: pass pair_read as NULL (requires pair_read[i] == i)."""
+    if identity_as_null:
+        assert np.array_equal(pair_read, np.arange(len(pair_read)))
+        pair_read = None
     if load_ref:
         gk.gk_load_reference(ctx, ref_loaded_ascii)
-    dr = device.encode_reads(ctx, reads, read_off, max_len=max_read_len)
+    if pairs_per_lane is not None:
+        gk.gk_set_option(ctx, gk.GK_OPT_PAIRS_PER_LANE, pairs_per_lane)
+    dr = device.encode_reads(ctx, reads, read_off, max_len=max_read_len, layout=layout)
     per_pair = not np.isscalar(e) and not isinstance(e, int)
     dp = device.upload_pairs(pair_read, cand_pos, e if per_pair else None, with_bits=with_bits)
     b = device.batch_for(dr, dp, e_uniform=0 if per_pair else int(e), max_read_len=max_read_len)
@@ -30,6 +37,8 @@ def run_gpu(ctx, ref_loaded_ascii, reads, read_off, pair_read, cand_pos, e, *, m
     torch.cuda.synchronize()
     a, s = device.results(dp)
     bits = dp.accept_bits.cpu().numpy().view(np.uint64) if with_bits else None
+    if pairs_per_lane is not None:
+        gk.gk_set_option(ctx, gk.GK_OPT_PAIRS_PER_LANE, 0)
     return a, s, bits
 
 
@@ -52,3 +61,39 @@ def concat_reads(seqs):
     np.cumsum(lens, out=off[1:])
     buf = np.frombuffer(b"".join(seqs), dtype=np.uint8) if seqs else np.zeros(0, np.uint8)
     return buf.copy(), off
+
+
+def run_gpu_mixed(ctx, reads, read_off, pair_read, cand_pos, e, *, max_read_len, layout=0,
+                  options=None, with_bits=False, repeats=1):
+    """gk_filter_mixed on a resident reference.  options: {GK_OPT_*: value},
+    reset to their defaults afterwards.  With repeats > 1 the call is
+    replayed, the outputs cleared in between, and every replay returned."""
+    import torch
+    defaults = {gk.GK_OPT_MIXED_TILE: 4096, gk.GK_OPT_MIXED_PAIRS_PER_LANE: 1,
+                gk.GK_OPT_MIXED_SORT_E: 1, gk.GK_OPT_MIXED_BLOCKS_PER_CU: 0,
+                gk.GK_OPT_MIXED_GRAPH: 1}
+    for k, v in (options or {}).items():
+        gk.gk_set_option(ctx, k, v)
+    try:
+        dr = device.encode_reads(ctx, reads, read_off, max_len=max_read_len, layout=layout)
+        per_pair = not np.isscalar(e) and not isinstance(e, int)
+        dp = device.upload_pairs(pair_read, cand_pos, e if per_pair else None,
+                                 with_bits=with_bits)
+        b = device.batch_for(dr, dp, e_uniform=0 if per_pair else int(e),
+                             max_read_len=max_read_len)
+        out = []
+        for _ in range(repeats):
+            dp.accept.fill_(0xEE)
+            dp.est.fill_(0x5A5A)
+            if dp.accept_bits is not None:
+                dp.accept_bits.fill_(-1)
+            torch.cuda.synchronize()
+            gk.gk_filter_mixed(ctx, b, None)
+            torch.cuda.synchronize()
+            a, s = device.results(dp)
+            bits = dp.accept_bits.cpu().numpy().view(np.uint64) if with_bits else None
+            out.append((a.copy(), s.copy(), bits))
+        return out if repeats > 1 else out[0]
+    finally:
+        for k in (options or {}):
+            gk.gk_set_option(ctx, k, defaults[k])

@@ -88,6 +88,18 @@ def test_errors(gkctx):
         with pytest.raises(gk.GkError) as ei:
             gk.gk_load_reference(ctx2, b"")
         assert ei.value.status == gk.GK_EINVAL
+        bad = device.batch_for(reads, pairs, e_uniform=0)
+        bad.read_layout = 7
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_filter(ctx2, bad)
+        assert ei.value.status == gk.GK_EINVAL
+        for opt, val in ((gk.GK_OPT_PAIRS_PER_LANE, -1), (gk.GK_OPT_PAIRS_PER_LANE, 65537),
+                         (999, 0)):
+            with pytest.raises(gk.GkError) as ei:
+                gk.gk_set_option(ctx2, opt, val)
+            assert ei.value.status == gk.GK_EINVAL
+        gk.gk_set_option(ctx2, gk.GK_OPT_PAIRS_PER_LANE, 5)
+        assert gk.gk_get_option(ctx2, gk.GK_OPT_PAIRS_PER_LANE) == 5
         torch.cuda.synchronize()
     finally:
         gk.gk_destroy(ctx2)
@@ -131,10 +143,12 @@ def test_per_pair_status(gkctx):
 
 
 @pytest.mark.gpu
-def test_encode_reads_layout(gkctx):
-    """gk_encode_reads against an independent numpy packing of the documented
-    layout: base i of a read in bits 2(i mod 16) of word i / 16, word w of
-    read r at w * pitch + r, A=0 C=1 G=2 T=3."""
+@pytest.mark.parametrize("layout", [0, 1], ids=["split", "interleaved"])
+def test_encode_reads_layout(gkctx, layout):
+    """gk_encode_reads against an independent packing of the documented
+    layouts: base i of a read in word i / 16 (word w of read r at
+    w * pitch + r), A=0 C=1 G=2 T=3; split: low code bit at bit i mod 16, high
+    bit at 16 + i mod 16; interleaved: code at bits 2(i mod 16), 2(i mod 16)+1."""
     from paper_2103_14978_amd import device
     rng = np.random.default_rng(9)
     seqs = []
@@ -146,7 +160,7 @@ def test_encode_reads_layout(gkctx):
         seqs.append(bytes(s))
     from gpu_cases import concat_reads
     reads, off = concat_reads(seqs)
-    dr = device.encode_reads(gkctx, reads, off, max_len=200)
+    dr = device.encode_reads(gkctx, reads, off, max_len=200, layout=layout)
     packed = dr.packed.cpu().numpy().view(np.uint32).reshape(-1, dr.pitch)
     lens = dr.read_len.cpu().numpy().view(np.uint16)[:len(seqs)]
     hasn = dr.has_n.cpu().numpy()[:len(seqs)]
@@ -154,10 +168,14 @@ def test_encode_reads_layout(gkctx):
     for r, s in enumerate(seqs):
         assert lens[r] == len(s)
         assert hasn[r] == int(any(ch not in code for ch in s))
-        want = np.zeros(packed.shape[0], np.uint64)
+        want = [0] * packed.shape[0]
         for i, ch in enumerate(s):
-            want[i // 16] |= np.uint64(code.get(ch, None) or 0) << np.uint64(2 * (i % 16))
-        assert np.array_equal(packed[:, r].astype(np.uint64), want), r
+            c = code.get(ch, 0)
+            if layout == 0:
+                want[i // 16] |= ((c & 1) << (i % 16)) | ((c >> 1) << (16 + i % 16))
+            else:
+                want[i // 16] |= c << (2 * (i % 16))
+        assert [int(x) for x in packed[:, r]] == want, r
 
 
 @pytest.mark.gpu

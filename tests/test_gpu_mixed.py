@@ -1,0 +1,146 @@
+"""The mixed-batch persistent filter (gk_filter_mixed) against the oracle,
+bit-exact on every pair, under every tuning the autotuner can choose."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import gen
+from gpu_cases import (assert_same, concat_reads, run_gpu_mixed, run_oracle, say)
+from paper_2103_14978_amd import gk
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c3_data():
+    ref = gen.c1_reference(20_000_000)
+    ps = gen.c3_pairs(ref, n_pairs=(1 << 16) + 777)       # ragged tail
+    ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, ps.e)
+    return ref, ps, ra, rs
+
+
+@pytest.fixture
+def c3(gkctx, c3_data):
+    """Config-3 pairs with their reference resident (other tests replace it)."""
+    gk.gk_load_reference(gkctx, c3_data[0])
+    return c3_data
+
+
+def test_config3_default(gkctx, c3):
+    ref, ps, ra, rs = c3
+    say("case: mixed config3 default tuning")
+    a, s, bits = run_gpu_mixed(gkctx, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, ps.e,
+                               max_read_len=300, with_bits=True)
+    assert_same(a, s, ra, rs, "mixed config3")
+    want = (ra == 1) | (ra == 2)
+    got = np.unpackbits(bits.view(np.uint8), bitorder="little")[:len(ra)].astype(bool)
+    assert np.array_equal(got, want)
+
+
+CANDIDATES = [dict(zip(("tile", "ppl", "sort_e", "bpc"), c))
+              for c in itertools.product((2048, 4096, 8192), (1, 2), (0, 1), (0, 1))]
+
+
+@pytest.mark.parametrize("cand", CANDIDATES, ids=lambda c: "t{tile}-p{ppl}-s{sort_e}-b{bpc}".format(**c))
+def test_config3_every_tuning(gkctx, c3, cand):
+    """Output is independent of the autotuner's choice."""
+    ref, ps, ra, rs = c3
+    say(f"case: mixed config3 tuning {cand}")
+    opts = {gk.GK_OPT_MIXED_TILE: cand["tile"], gk.GK_OPT_MIXED_PAIRS_PER_LANE: cand["ppl"],
+            gk.GK_OPT_MIXED_SORT_E: cand["sort_e"], gk.GK_OPT_MIXED_BLOCKS_PER_CU: cand["bpc"],
+            gk.GK_OPT_MIXED_GRAPH: cand["tile"] != 2048}
+    a, s, _ = run_gpu_mixed(gkctx, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, ps.e,
+                            max_read_len=300, options=opts)
+    assert_same(a, s, ra, rs, f"mixed {cand}")
+
+
+def test_graph_replays_match_eager(gkctx, c3):
+    """Replays of the captured graph, with the outputs cleared by other
+    kernels in between, all equal the direct launch."""
+    ref, ps, ra, rs = c3
+    say("case: mixed graph replays")
+    eager = run_gpu_mixed(gkctx, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, ps.e,
+                          max_read_len=300, options={gk.GK_OPT_MIXED_GRAPH: 0})
+    reps = run_gpu_mixed(gkctx, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, ps.e,
+                         max_read_len=300, repeats=4)
+    for k, (a, s, _) in enumerate(reps):
+        assert_same(a, s, eager[0], eager[1], f"replay {k}")
+    assert_same(eager[0], eager[1], ra, rs, "eager")
+
+
+def test_interleaved_layout_and_uniform_e(gkctx, c3):
+    ref, ps, _, _ = c3
+    for e in (0, 3, 12):
+        say(f"case: mixed interleaved uniform e={e}")
+        a, s, _ = run_gpu_mixed(gkctx, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, e,
+                                max_read_len=300, layout=1)
+        ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, e)
+        assert_same(a, s, ra, rs, f"interleaved e={e}")
+
+
+def test_residuals_status_and_long_reads(gkctx):
+    """Pairs with more than 31 shifts (residual pass), unknown bases, windows
+    past the end, invalid lengths, reads up to 512 bases (16 words)."""
+    rng = np.random.default_rng(31)
+    ref = bytearray(rng.choice(np.frombuffer(b"ACGT", np.uint8), 400_000).tobytes())
+    for p in rng.integers(0, len(ref), 40):
+        ref[int(p)] = ord("N")
+    ref = np.frombuffer(bytes(ref), np.uint8).copy()
+    gk.gk_load_reference(gkctx, ref)
+    seqs, prs, poss, es = [], [], [], []
+    for k in range(6000):
+        m = int(rng.choice([1, 7, 31, 32, 33, 64, 100, 129, 250, 300, 320, 400, 511, 512]))
+        p = int(rng.integers(0, len(ref) - m))
+        s = bytearray(ref[p:p + m].tobytes())
+        for _ in range(int(rng.integers(0, 6))):
+            s[int(rng.integers(0, m))] = b"ACGT"[int(rng.integers(0, 4))]
+        if k % 97 == 0:
+            s[0] = ord("N")
+        seqs.append(bytes(s))
+        prs.append(k)
+        poss.append(p if k % 53 else len(ref) - m // 2)
+        es.append(int(rng.integers(0, 60)))
+    seqs.append(b"")
+    prs.append(len(seqs) - 1)
+    poss.append(0)
+    es.append(3)
+    prs.append(len(seqs) + 10)      # read index out of range
+    poss.append(0)
+    es.append(3)
+    reads, off = concat_reads(seqs)
+    pr, pos = np.array(prs, np.uint32), np.array(poss, np.uint32)
+    e = np.array(es, np.uint8)
+    say("case: mixed residuals / status / long reads")
+    a, s, bits = run_gpu_mixed(gkctx, reads, off, pr, pos, e, max_read_len=512,
+                               with_bits=True, options={gk.GK_OPT_MIXED_TILE: 2048})
+    ra, rs = run_oracle(ref, reads, off, pr, pos, e)
+    assert_same(a, s, ra, rs, "residuals")
+    assert set(np.unique(ra)) == {0, 1, 2, 3}
+
+
+def test_tuner_report_and_cache(gkctx, c3, tmp_path):
+    import torch
+    from paper_2103_14978_amd import device
+    ref, ps, ra, rs = c3
+    dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=300)
+    dp = device.upload_pairs(ps.pair_read, ps.cand_pos, ps.e)
+    b = device.batch_for(dr, dp, max_read_len=300)
+    cache = str(tmp_path / "tune.jsonl")
+    say("case: tuner measured")
+    rep = json.loads(gk.gk_tune_mixed(gkctx, b, None, sample_pairs=1 << 15, cache_path=cache))
+    assert rep["source"] == "measured" and len(rep["candidates"]) == 24
+    chosen = (rep["tile"], rep["ppl"], rep["sort_e"], rep["blocks_per_cu"])
+    assert gk.gk_get_option(gkctx, gk.GK_OPT_MIXED_TILE) == rep["tile"]
+    rep2 = json.loads(gk.gk_tune_mixed(gkctx, b, None, sample_pairs=1 << 15, cache_path=cache))
+    assert rep2["source"] == "cache"
+    assert (rep2["tile"], rep2["ppl"], rep2["sort_e"], rep2["blocks_per_cu"]) == chosen
+    gk.gk_filter_mixed(gkctx, b, None)
+    torch.cuda.synchronize()
+    a, s = device.results(dp)
+    assert_same(a, s, ra, rs, "after tuning")
+    for opt, val in ((gk.GK_OPT_MIXED_TILE, 4096), (gk.GK_OPT_MIXED_PAIRS_PER_LANE, 1),
+                     (gk.GK_OPT_MIXED_SORT_E, 1), (gk.GK_OPT_MIXED_BLOCKS_PER_CU, 0)):
+        gk.gk_set_option(gkctx, opt, val)

@@ -184,3 +184,39 @@ def test_config3_scaled_plain(gkctx):
                       max_read_len=300)
     ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, ps.e)
     assert_same(a, s, ra, rs, "config3 plain")
+
+
+@pytest.mark.parametrize("layout", [0, 1], ids=["split", "interleaved"])
+@pytest.mark.parametrize("ppl", [0, 1, 2, 7, 65536])
+def test_layouts_and_grid_shapes(gkctx, layout, ppl):
+    """Both read layouts, and grids from one pair per lane to many pairs per
+    lane with loads in flight, give the same bit-exact results: config 0
+    pairs plus a mixed-length, per-pair-e set in one launch."""
+    rng = np.random.default_rng(79)
+    ref = gen.c0_reference()
+    ps = gen.c0_pairs(ref, n_reads=3001)
+    say(f"case: layout={layout} pairs_per_lane={ppl} config0")
+    a, s, bits = run_gpu(gkctx, ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, 2,
+                         layout=layout, pairs_per_lane=ppl, with_bits=True,
+                         identity_as_null=(ppl % 2 == 1))
+    ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, 2)
+    assert_same(a, s, ra, rs, f"config0 layout={layout} ppl={ppl}")
+    want = (ra == 1) | (ra == 2)
+    got = np.unpackbits(bits.view(np.uint8), bitorder="little")[:len(ra)].astype(bool)
+    assert np.array_equal(got, want)
+    seqs, prs, poss, es = [], [], [], []
+    for m in (5, 31, 33, 64, 100, 129, 200):
+        reads, off, pr, pos = _sweep_pairs(ref, m, 97, rng)
+        base = len(seqs)
+        for i in range(len(pr)):
+            seqs.append(reads[off[i]:off[i + 1]].tobytes())
+        prs.append(pr + base)
+        poss.append(pos)
+        es.append(rng.integers(0, 40, len(pr)).astype(np.uint8))
+    reads, off = concat_reads(seqs)
+    pr, pos, e = np.concatenate(prs), np.concatenate(poss), np.concatenate(es)
+    say(f"case: layout={layout} pairs_per_lane={ppl} mixed")
+    a, s, _ = run_gpu(gkctx, ref, reads, off, pr, pos, e, max_read_len=200, layout=layout,
+                      pairs_per_lane=ppl, load_ref=False)
+    ra, rs = run_oracle(ref, reads, off, pr, pos, e)
+    assert_same(a, s, ra, rs, f"mixed layout={layout} ppl={ppl}")
