@@ -43,6 +43,7 @@ extern "C" {
 #define GK_EDEVICE  (-3)   /* HIP runtime or device error                    */
 #define GK_ENOREF   (-4)   /* no reference loaded                            */
 #define GK_ERANGE   (-5)   /* size beyond a documented limit                 */
+#define GK_ETIMEOUT (-7)   /* gk_server_wait: not finished within the timeout */
 
 /* Per-pair result codes written to gk_batch.accept. */
 #define GK_REJECT     0u   /* edit estimate > e                              */
@@ -228,6 +229,83 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream);
  */
 int gk_tune_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream, uint64_t sample_pairs,
                   const char *cache_path, char *report, size_t report_cap);
+
+/*
+ * Serving loop.  Requests of varying size, read length and threshold are
+ * submitted from any thread; the server keeps the reference (the context's)
+ * and each admitted request's state on the GPU and reports per-request times.
+ *
+ * GK_SERVER_BATCHED: requests are admitted in arrival order when a slot is
+ * free and the device arena (device_budget_bytes, allocated at start) has
+ * room for the request's footprint; admitted requests are copied in and
+ * encoded on a copy stream while earlier ones are filtered, and every
+ * scheduling tick filters all loaded requests together in one persistent
+ * launch (the mixed-batch kernel over a table of requests, replayed from a
+ * hipGraph), with at most two ticks in flight; results are copied back and the
+ * slot and memory freed as each tick completes.
+ * GK_SERVER_SEQUENTIAL: the per-request baseline: one request at a time, copy
+ * in, encode, one plain filter launch, copy out, on one stream.
+ * Both give the same bytes as gk_filter on the same pairs.
+ */
+#define GK_SERVER_BATCHED    0u
+#define GK_SERVER_SEQUENTIAL 1u
+
+typedef struct gk_server gk_server;
+
+typedef struct gk_request {
+    const char     *reads;         /* HOST: read r = reads[read_off[r] ..
+                                      read_off[r+1]), ASCII                 */
+    const uint64_t *read_off;      /* HOST: n_reads + 1 offsets              */
+    uint32_t        n_reads;       /* < 2^30                                 */
+    uint32_t        e;             /* threshold of every pair, 0..255        */
+    const uint32_t *pair_read;     /* HOST: n_pairs read indices, or NULL:
+                                      pair i uses read i                     */
+    const uint32_t *cand_pos;      /* HOST: n_pairs window starts            */
+    uint64_t        n_pairs;       /* < 2^30                                 */
+    uint8_t        *accept;        /* HOST out: n_pairs result codes         */
+    uint16_t       *est;           /* HOST out: n_pairs estimates            */
+    int64_t         t_arrival_us;  /* arrival time on gk_clock_us()'s clock
+                                      (latency is measured from it), or 0:
+                                      the time of submission                 */
+} gk_request;
+
+typedef struct gk_request_stats {
+    int     status;                /* GK_OK, or GK_EDEVICE if the server failed */
+    uint64_t n_pairs;
+    int64_t t_submit_us;           /* arrival time (t_arrival_us or submit)  */
+    int64_t t_admit_us;            /* admitted to a slot                     */
+    int64_t t_done_us;             /* results in the caller's host buffers   */
+} gk_request_stats;
+
+/* Start a server on ctx's device and resident reference (which must not be
+   replaced while the server runs).  max_slots 1..256 requests in flight,
+   max_read_len 1..512 (longer requests are refused), device_budget_bytes >=
+   1 MiB, mode GK_SERVER_*.  Starts its worker threads. */
+int gk_server_start(gk_ctx *ctx, uint64_t device_budget_bytes, uint32_t max_slots,
+                    uint32_t max_read_len, uint32_t mode, gk_server **out);
+
+/* Queue a request; returns at once with a ticket.  The host buffers it names
+   must stay valid until gk_server_wait returns for the ticket.  GK_EINVAL for
+   bad pointers or sizes, GK_ERANGE for reads longer than the server's
+   max_read_len or a footprint larger than the whole budget. */
+int gk_server_submit(gk_server *srv, const gk_request *req, uint64_t *ticket);
+
+/* Wait for a ticket (timeout_us < 0: no limit).  GK_ETIMEOUT leaves the
+   request queued (wait again); any other return releases the ticket.
+   Returns the request's status; stats may be NULL.  Thread-safe. */
+int gk_server_wait(gk_server *srv, uint64_t ticket, int64_t timeout_us,
+                   gk_request_stats *stats);
+
+/* Ticks launched, most requests in one tick, pairs finished. */
+int gk_server_counters(gk_server *srv, uint64_t *ticks, uint64_t *max_requests_per_tick,
+                       uint64_t *pairs_done);
+
+/* Finish every submitted request, stop the threads, free the server. */
+int gk_server_stop(gk_server *srv);
+
+/* The clock of gk_request.t_arrival_us and gk_request_stats: microseconds of
+   a monotonic clock (CLOCK_MONOTONIC on Linux). */
+int64_t gk_clock_us(void);
 
 #ifdef __cplusplus
 }

@@ -14,30 +14,9 @@ namespace {
 
 thread_local std::string g_create_error;
 
-// Makes the context's device current for the duration of a call and restores
-// the caller's device afterwards.
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = false;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess)
-            prev = -1;
-        ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0)
-            (void)hipSetDevice(prev);
-    }
-};
+using DeviceGuard = DeviceScope;
 
-int fail(gk_ctx *ctx, int code, const std::string &msg)
-{
-    if (ctx)
-        ctx->err = msg;
-    return code;
-}
+int fail(gk_ctx *ctx, int code, const std::string &msg) { return gk_detail_fail(ctx, code, msg); }
 
 int hip_fail(gk_ctx *ctx, hipError_t e, const char *what)
 {
@@ -331,6 +310,7 @@ int mixed_args(gk_ctx *ctx, const MixedConfig &c, uint32_t wmax, uint32_t layout
         per_cu = 1;
     const uint32_t bpc = c.blocks_per_cu && (int)c.blocks_per_cu < per_cu ? c.blocks_per_cu
                                                                           : (uint32_t)per_cu;
+    x.table = nullptr;
     x.tile_counter = ctx->d_mixed_counters;
     x.resid_count = ctx->d_mixed_counters + 1;
     x.resid_list = ctx->d_resid;

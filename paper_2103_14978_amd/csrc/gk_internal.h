@@ -54,6 +54,31 @@ struct gk_ctx {
     std::vector<uint8_t> graph_key;
 };
 
+// Makes a device current for a scope and restores the caller's device.
+struct DeviceScope {
+    int prev = -1;
+    bool ok = false;
+    explicit DeviceScope(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess)
+            prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceScope()
+    {
+        if (prev >= 0)
+            (void)hipSetDevice(prev);
+    }
+};
+
+// Records msg as the context's last error and returns code.
+inline int gk_detail_fail(gk_ctx *ctx, int code, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    return code;
+}
+
 namespace gkd {
 
 struct FilterArgs {
@@ -79,7 +104,18 @@ struct FilterArgs {
     unsigned long long *accept_bits;
 };
 
+// A table of batches filtered by one persistent launch (the serving loop's
+// tick): batch b owns the launch's tiles [prefix[b], prefix[b+1]).
+constexpr uint32_t MAX_TABLE_BATCHES = 256;
+struct BatchTable {
+    uint32_t n_batches;
+    uint32_t pad_[3];
+    uint32_t prefix[MAX_TABLE_BATCHES + 1];
+    FilterArgs args[MAX_TABLE_BATCHES];
+};
+
 struct MixedArgs {
+    const BatchTable *table;     // device table, or nullptr for the single batch
     uint32_t *tile_counter;      // zeroed by the launch sequence
     uint32_t *resid_count;       // zeroed by the launch sequence
     uint32_t *resid_list;        // capacity >= pairs per launch
@@ -97,6 +133,10 @@ hipError_t launch_mixed(const FilterArgs &a, const MixedArgs &x, uint32_t wmax, 
                         hipStream_t s);
 hipError_t mixed_blocks_per_cu(uint32_t wmax, uint32_t layout, uint32_t tile, uint32_t ppl,
                                int *out);
+// Table launch sequence (reset, persistent kernel, residual pass) for the
+// table at x.table; the tile count is read from the table on the device, so
+// the sequence can be captured once and replayed with new table contents.
+hipError_t launch_mixed_table(const MixedArgs &x, uint32_t wmax, uint32_t layout, hipStream_t s);
 size_t mixed_lds_size(uint32_t tile);
 
 // Launch the plain filter with `words` 32-base words per mask (1..16).

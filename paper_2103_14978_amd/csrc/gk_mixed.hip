@@ -100,8 +100,24 @@ __device__ __forceinline__ void run_chunk(const FilterArgs &a, uint32_t w, uint3
 #undef GK_CASE
 }
 
+// Batch of a tile in a table launch: the last b with prefix[b] <= tile (empty
+// batches share their prefix with the next one, so the last match is the
+// batch that owns the tile).
+__device__ __forceinline__ uint32_t table_batch(const BatchTable *t, uint32_t tile)
+{
+    uint32_t lo = 0, hi = t->n_batches;          // prefix[hi] > tile
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (t->prefix[mid] <= tile)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
 template <int WMAX, int L, int PPL>
-__global__ __launch_bounds__(256) void k_mixed(FilterArgs a, MixedArgs x)
+__global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
 {
     extern __shared__ uint32_t lds_raw[];
     MixedLds &s = *reinterpret_cast<MixedLds *>(lds_raw);
@@ -112,7 +128,7 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a, MixedArgs x)
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
-    const uint32_t n = (uint32_t)a.n_pairs;
+    const uint32_t n_tiles = x.table ? x.table->prefix[x.table->n_batches] : x.n_tiles;
 
     while (true) {
         if (tid == 0)
@@ -121,9 +137,18 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a, MixedArgs x)
             s.hist[b] = 0;
         __syncthreads();
         const uint32_t tile = s.tile;
-        if (tile >= x.n_tiles)
+        if (tile >= n_tiles)
             break;
-        const uint32_t base = tile * x.tile;
+        // Residual entries are launch-wide ids tile * T + slot.
+        const uint32_t gbase = tile * x.tile;
+        FilterArgs a = a0;
+        uint32_t base = gbase;
+        if (x.table) {
+            const uint32_t b = table_batch(x.table, tile);
+            a = x.table->args[b];
+            base = (tile - x.table->prefix[b]) * x.tile;
+        }
+        const uint32_t n = (uint32_t)a.n_pairs;
 
         // 1. classify
         for (uint32_t j = tid; j < x.tile; j += 256) {
@@ -143,7 +168,7 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a, MixedArgs x)
                     const uint32_t kmax = p.e < m - 1u ? p.e : m - 1u;
                     const uint32_t w = (m + 31u) / 32u;
                     if (kmax > 31u || w > (uint32_t)WMAX) {
-                        x.resid_list[atomicAdd(x.resid_count, 1u)] = i;
+                        x.resid_list[atomicAdd(x.resid_count, 1u)] = gbase + j;
                     } else {
                         key = (w - 1u) * 32u + (x.sort_e ? kmax : 0u);
                         atomicAdd(&s.hist[key], 1u);
@@ -241,12 +266,20 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a, MixedArgs x)
 }
 
 template <int W, int L>
-__global__ __launch_bounds__(256) void k_residual(FilterArgs a, const uint32_t *list,
+__global__ __launch_bounds__(256) void k_residual(FilterArgs a0, const BatchTable *table,
+                                                  uint32_t tile_size, const uint32_t *list,
                                                   const uint32_t *count)
 {
     const uint32_t total = *count;
     for (uint32_t j = blockIdx.x * 256u + threadIdx.x; j < total; j += gridDim.x * 256u) {
-        const uint32_t i = list[j];
+        uint32_t i = list[j];
+        FilterArgs a = a0;
+        if (table) {
+            const uint32_t tile = i / tile_size;
+            const uint32_t b = table_batch(table, tile);
+            a = table->args[b];
+            i -= table->prefix[b] * tile_size;
+        }
         const PairIdx p = load_idx(a, i);
         PairData<W> d;
         load_data<W>(a, p, d);
@@ -317,7 +350,8 @@ hipError_t launch_mixed_wl(const FilterArgs &a, const MixedArgs &x0, hipStream_t
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         hipLaunchKernelGGL((k_residual<WMAX, L>), dim3(x.resid_blocks), dim3(256), 0, s, c,
-                           (const uint32_t *)x.resid_list, (const uint32_t *)x.resid_count);
+                           (const BatchTable *)nullptr, x.tile, (const uint32_t *)x.resid_list,
+                           (const uint32_t *)x.resid_count);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (a.accept_bits) {
@@ -329,6 +363,33 @@ hipError_t launch_mixed_wl(const FilterArgs &a, const MixedArgs &x0, hipStream_t
         }
     }
     return hipSuccess;
+}
+
+template <int WMAX, int L>
+hipError_t launch_table_wl(const MixedArgs &x, hipStream_t s)
+{
+    FilterArgs none{};
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, x.tile_counter, x.resid_count);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    if constexpr (WMAX <= 10) {
+        if (x.ppl == 2)
+            hipLaunchKernelGGL((k_mixed<WMAX, L, 2>), dim3(x.blocks), dim3(256),
+                               mixed_lds_bytes(x.tile), s, none, x);
+        else
+            hipLaunchKernelGGL((k_mixed<WMAX, L, 1>), dim3(x.blocks), dim3(256),
+                               mixed_lds_bytes(x.tile), s, none, x);
+    } else {
+        hipLaunchKernelGGL((k_mixed<WMAX, L, 1>), dim3(x.blocks), dim3(256),
+                           mixed_lds_bytes(x.tile), s, none, x);
+    }
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL((k_residual<WMAX, L>), dim3(x.resid_blocks), dim3(256), 0, s, none,
+                       x.table, x.tile, (const uint32_t *)x.resid_list,
+                       (const uint32_t *)x.resid_count);
+    return hipGetLastError();
 }
 
 template <int L>
@@ -369,6 +430,19 @@ hipError_t mixed_blocks_per_cu(uint32_t wmax, uint32_t layout, uint32_t tile, ui
                   : occupancy_wl<10, GK_READS_SPLIT>(tile, ppl, out);
     return il ? occupancy_wl<16, GK_READS_INTERLEAVED>(tile, ppl, out)
               : occupancy_wl<16, GK_READS_SPLIT>(tile, ppl, out);
+}
+
+hipError_t launch_mixed_table(const MixedArgs &x, uint32_t wmax, uint32_t layout, hipStream_t s)
+{
+    const bool il = layout == GK_READS_INTERLEAVED;
+    if (wmax <= 4)
+        return il ? launch_table_wl<4, GK_READS_INTERLEAVED>(x, s)
+                  : launch_table_wl<4, GK_READS_SPLIT>(x, s);
+    if (wmax <= 10)
+        return il ? launch_table_wl<10, GK_READS_INTERLEAVED>(x, s)
+                  : launch_table_wl<10, GK_READS_SPLIT>(x, s);
+    return il ? launch_table_wl<16, GK_READS_INTERLEAVED>(x, s)
+              : launch_table_wl<16, GK_READS_SPLIT>(x, s);
 }
 
 hipError_t launch_mixed(const FilterArgs &a, const MixedArgs &x, uint32_t wmax, uint32_t layout,

@@ -1,0 +1,696 @@
+// Serving loop for the GateKeeper-GPU filter: admission by device memory and
+// slots, request state on the GPU, continuous batching of every loaded
+// request into the persistent mixed-batch kernel.
+//
+// Threads (batched mode):
+//   loader     admits pending requests in arrival order when a slot is free
+//              and the device arena has room, copies the request in on the
+//              copy stream and encodes its reads there (gk_encode_reads'
+//              kernel), then marks it ready;
+//   scheduler  every tick takes all ready requests, fills a batch table in
+//              pinned memory and replays a captured graph on the compute
+//              stream (table copy -> reset -> persistent kernel -> residual
+//              pass); at most two ticks are in flight, the two table buffers
+//              alternate;
+//   completer  waits for ticks in order, copies each request's results back,
+//              frees its arena range and slot, wakes its waiter.
+// So copies of new requests overlap the kernel of the current tick, and a
+// request arriving while others run joins the next tick.
+//
+// Sequential mode (the per-request baseline): the loader alone takes one
+// request at a time through copy in, encode, one plain gk_filter launch and
+// copy out on a single stream.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "gk_internal.h"
+
+namespace {
+
+int64_t now_us()
+{
+    return std::chrono::duration_cast<std::chrono::microseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+constexpr uint64_t ALIGN = 256;
+uint64_t align_up(uint64_t v) { return (v + ALIGN - 1) & ~(ALIGN - 1); }
+
+// First-fit allocator over one device region; free ranges are coalesced.
+class Arena {
+  public:
+    void init(uint64_t size)
+    {
+        free_.clear();
+        free_[0] = size;
+        size_ = size;
+    }
+    bool alloc(uint64_t n, uint64_t *off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const uint64_t rest = it->second - n, at = it->first + n;
+                free_.erase(it);
+                if (rest)
+                    free_[at] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n)
+    {
+        auto it = free_.emplace(off, n).first;
+        auto next = std::next(it);
+        if (next != free_.end() && it->first + it->second == next->first) {
+            it->second += next->second;
+            free_.erase(next);
+        }
+        if (it != free_.begin()) {
+            auto prev = std::prev(it);
+            if (prev->first + prev->second == it->first) {
+                prev->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t size() const { return size_; }
+
+  private:
+    std::map<uint64_t, uint64_t> free_;
+    uint64_t size_ = 0;
+};
+
+struct Req {
+    uint64_t ticket = 0;
+    gk_request r{};
+    uint32_t max_len = 0, rows = 0, pitch = 0;
+    uint64_t ascii_bytes = 0, footprint = 0, arena_off = 0;
+    uint8_t *d_ascii = nullptr;
+    uint64_t *d_off = nullptr;
+    uint32_t *d_packed = nullptr;
+    uint16_t *d_len = nullptr;
+    uint8_t *d_hasn = nullptr;
+    uint32_t *d_pr = nullptr, *d_pos = nullptr;
+    uint8_t *d_acc = nullptr;
+    uint16_t *d_est = nullptr;
+    hipEvent_t ready = nullptr;
+    int64_t t_submit = 0, t_admit = 0, t_done = 0;
+    int status = GK_OK;
+    bool done = false, admitted = false;
+};
+
+struct Tick {
+    int buf = 0;
+    std::vector<Req *> reqs;
+};
+
+}  // namespace
+
+struct gk_server {
+    gk_ctx *ctx = nullptr;
+    uint32_t mode = GK_SERVER_BATCHED;
+    uint32_t max_slots = 0, max_read_len = 0, wmax = 0;
+    uint64_t budget = 0;
+    Arena arena;
+    uint8_t *d_arena = nullptr;
+    hipStream_t s_copy = nullptr, s_compute = nullptr, s_d2h = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req *> pending, ready;
+    std::deque<Tick> inflight;
+    std::unordered_map<uint64_t, Req *> reqs;
+    uint32_t slots_used = 0;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    std::string err;
+    std::thread loader, scheduler, completer;
+    // tick resources, double-buffered
+    gkd::BatchTable *h_table[2] = {nullptr, nullptr};
+    gkd::BatchTable *d_table[2] = {nullptr, nullptr};
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    hipEvent_t tick_done[2] = {nullptr, nullptr};
+    bool buf_busy[2] = {false, false};
+    uint32_t *d_counters = nullptr;
+    uint32_t *d_resid = nullptr;
+    gkd::MixedArgs margs{};
+    uint64_t ticks = 0, tick_req_max = 0, pairs_done = 0;
+    int tick_buf = 0;
+};
+
+namespace {
+
+// Device footprint of a request, laid out in this order inside its arena
+// range: ASCII, offsets, packed reads, lengths, unknown flags, pair reads,
+// positions, accept codes, estimates.
+void plan(Req *q)
+{
+    const gk_request &r = q->r;
+    q->ascii_bytes = r.read_off[r.n_reads];
+    uint32_t mx = 1;
+    for (uint32_t i = 0; i < r.n_reads; ++i) {
+        const uint64_t len = r.read_off[i + 1] - r.read_off[i];
+        if (len > mx)
+            mx = (uint32_t)(len < 0xFFFFu ? len : 0xFFFFu);
+    }
+    q->max_len = mx;
+    q->rows = (mx + 15) / 16;
+    q->pitch = (r.n_reads + 63) / 64 * 64;
+    q->footprint = align_up(q->ascii_bytes ? q->ascii_bytes : 4) +
+                   align_up(8ull * (r.n_reads + 1)) + align_up(4ull * q->rows * q->pitch) +
+                   align_up(2ull * r.n_reads) + align_up(r.n_reads) +
+                   (r.pair_read ? align_up(4 * r.n_pairs) : 0) + align_up(4 * r.n_pairs) +
+                   align_up(r.n_pairs) + align_up(2 * r.n_pairs);
+}
+
+void place(gk_server *s, Req *q)
+{
+    uint8_t *p = s->d_arena + q->arena_off;
+    const gk_request &r = q->r;
+    q->d_ascii = p;
+    p += align_up(q->ascii_bytes ? q->ascii_bytes : 4);
+    q->d_off = (uint64_t *)p;
+    p += align_up(8ull * (r.n_reads + 1));
+    q->d_packed = (uint32_t *)p;
+    p += align_up(4ull * q->rows * q->pitch);
+    q->d_len = (uint16_t *)p;
+    p += align_up(2ull * r.n_reads);
+    q->d_hasn = p;
+    p += align_up(r.n_reads);
+    q->d_pr = nullptr;
+    if (r.pair_read) {
+        q->d_pr = (uint32_t *)p;
+        p += align_up(4 * r.n_pairs);
+    }
+    q->d_pos = (uint32_t *)p;
+    p += align_up(4 * r.n_pairs);
+    q->d_acc = p;
+    p += align_up(r.n_pairs);
+    q->d_est = (uint16_t *)p;
+}
+
+gkd::FilterArgs args_for(const gk_server *s, const Req *q)
+{
+    const gk_ctx *c = s->ctx;
+    gkd::FilterArgs a{};
+    a.ref_planes = c->ref_planes;
+    a.ref_unk = c->ref_unk;
+    a.ref_len = c->ref_len;
+    a.ref_has_unknown = c->ref_unknown > 0;
+    a.n_reads = q->r.n_reads;
+    a.pitch = q->pitch;
+    a.e_uniform = q->r.e;
+    a.max_read_len = s->max_read_len;
+    a.rows = q->rows;
+    a.reads = q->d_packed;
+    a.read_len = q->d_len;
+    a.read_has_n = q->d_hasn;
+    a.pair_read = q->d_pr;
+    a.cand_pos = q->d_pos;
+    a.e_pair = nullptr;
+    a.n_pairs = q->r.n_pairs;
+    a.accept = q->d_acc;
+    a.est = q->d_est;
+    a.accept_bits = nullptr;
+    return a;
+}
+
+// Copy a request in and encode its reads on `st` (caller thread blocks only
+// for the pageable host copies).
+hipError_t load_request(gk_server *s, Req *q, hipStream_t st)
+{
+    const gk_request &r = q->r;
+    hipError_t e = hipSuccess;
+    if (q->ascii_bytes)
+        e = hipMemcpyAsync(q->d_ascii, r.reads, q->ascii_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(q->d_off, r.read_off, 8ull * (r.n_reads + 1), hipMemcpyHostToDevice,
+                           st);
+    if (e == hipSuccess && r.pair_read)
+        e = hipMemcpyAsync(q->d_pr, r.pair_read, 4 * r.n_pairs, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(q->d_pos, r.cand_pos, 4 * r.n_pairs, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = gkd::launch_encode_reads(q->d_ascii, q->d_off, r.n_reads, q->pitch, q->rows,
+                                     GK_READS_SPLIT, q->d_packed, q->d_len, q->d_hasn, st);
+    return e;
+}
+
+hipError_t copy_out(Req *q, hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(q->r.accept, q->d_acc, q->r.n_pairs, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(q->r.est, q->d_est, 2 * q->r.n_pairs, hipMemcpyDeviceToHost, st);
+    return e;
+}
+
+void finish(gk_server *s, Req *q, int status)
+{
+    // caller holds s->mu
+    q->status = status;
+    q->t_done = now_us();
+    q->done = true;
+    if (q->admitted) {
+        s->arena.release(q->arena_off, q->footprint);
+        s->slots_used--;
+        q->admitted = false;
+    }
+    s->pairs_done += q->r.n_pairs;
+}
+
+void fail_all(gk_server *s, const std::string &msg)
+{
+    // caller holds s->mu: a device error ends the server's work
+    s->err = msg;
+    for (auto *q : s->pending)
+        finish(s, q, GK_EDEVICE);
+    for (auto *q : s->ready)
+        finish(s, q, GK_EDEVICE);
+    for (auto &t : s->inflight)
+        for (auto *q : t.reqs)
+            finish(s, q, GK_EDEVICE);
+    s->pending.clear();
+    s->ready.clear();
+    s->inflight.clear();
+    s->stopping = true;
+    s->cv.notify_all();
+}
+
+void loader_main(gk_server *s)
+{
+    DeviceScope dev(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        s->cv.wait(lk, [&] { return s->stopping || !s->pending.empty(); });
+        if (s->stopping)
+            break;
+        Req *q = s->pending.front();
+        uint64_t off = 0;
+        // Admission in arrival order: wait for a slot and arena room.
+        s->cv.wait(lk, [&] {
+            return s->stopping ||
+                   (s->slots_used < s->max_slots && s->arena.alloc(q->footprint, &off));
+        });
+        if (s->stopping)
+            break;
+        s->pending.pop_front();
+        s->slots_used++;
+        q->admitted = true;
+        q->arena_off = off;
+        q->t_admit = now_us();
+        place(s, q);
+        lk.unlock();
+
+        hipError_t e = load_request(s, q, s->s_copy);
+        if (s->mode == GK_SERVER_SEQUENTIAL) {
+            // One request at a time on one stream: copy in, encode, filter, copy out.
+            if (e == hipSuccess) {
+                const gkd::FilterArgs a = args_for(s, q);
+                e = gkd::launch_filter(a, s->wmax, GK_READS_SPLIT, 0, s->s_copy);
+            }
+            if (e == hipSuccess)
+                e = copy_out(q, s->s_copy);
+            if (e == hipSuccess)
+                e = hipStreamSynchronize(s->s_copy);
+            lk.lock();
+            if (e != hipSuccess) {
+                finish(s, q, GK_EDEVICE);
+                fail_all(s, std::string("server: ") + hipGetErrorName(e));
+                break;
+            }
+            finish(s, q, GK_OK);
+            s->cv.notify_all();
+            continue;
+        }
+        if (e == hipSuccess)
+            e = hipEventRecord(q->ready, s->s_copy);
+        lk.lock();
+        if (e != hipSuccess) {
+            finish(s, q, GK_EDEVICE);
+            fail_all(s, std::string("server load: ") + hipGetErrorName(e));
+            break;
+        }
+        s->ready.push_back(q);
+        s->cv.notify_all();
+    }
+}
+
+void scheduler_main(gk_server *s)
+{
+    DeviceScope dev(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        s->cv.wait(lk, [&] {
+            return s->stopping || (!s->ready.empty() && !s->buf_busy[s->tick_buf]);
+        });
+        if (s->stopping)
+            break;
+        Tick t;
+        t.buf = s->tick_buf;
+        // At most 256 requests and 2^20 tiles per tick (launch-wide pair ids
+        // tile * 2048 + slot stay below 2^31).
+        uint64_t tick_tiles = 0;
+        while (!s->ready.empty() && t.reqs.size() < gkd::MAX_TABLE_BATCHES) {
+            const uint64_t nt = (s->ready.front()->r.n_pairs + s->margs.tile - 1) / s->margs.tile;
+            if (!t.reqs.empty() && tick_tiles + nt > (1u << 20))
+                break;
+            tick_tiles += nt;
+            t.reqs.push_back(s->ready.front());
+            s->ready.pop_front();
+        }
+        s->buf_busy[t.buf] = true;
+        s->tick_buf ^= 1;
+        lk.unlock();
+
+        gkd::BatchTable *h = s->h_table[t.buf];
+        h->n_batches = (uint32_t)t.reqs.size();
+        uint32_t tiles = 0;
+        for (size_t b = 0; b < t.reqs.size(); ++b) {
+            h->prefix[b] = tiles;
+            h->args[b] = args_for(s, t.reqs[b]);
+            tiles += (uint32_t)((t.reqs[b]->r.n_pairs + s->margs.tile - 1) / s->margs.tile);
+        }
+        h->prefix[t.reqs.size()] = tiles;
+        hipError_t e = hipSuccess;
+        for (auto *q : t.reqs)
+            if (e == hipSuccess)
+                e = hipStreamWaitEvent(s->s_compute, q->ready, 0);
+        if (e == hipSuccess)
+            e = hipGraphLaunch(s->graph[t.buf], s->s_compute);
+        if (e == hipSuccess)
+            e = hipEventRecord(s->tick_done[t.buf], s->s_compute);
+        lk.lock();
+        if (e != hipSuccess) {
+            s->inflight.push_back(std::move(t));
+            fail_all(s, std::string("server tick: ") + hipGetErrorName(e));
+            break;
+        }
+        s->ticks++;
+        if (t.reqs.size() > s->tick_req_max)
+            s->tick_req_max = t.reqs.size();
+        s->inflight.push_back(std::move(t));
+        s->cv.notify_all();
+    }
+}
+
+void completer_main(gk_server *s)
+{
+    DeviceScope dev(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        s->cv.wait(lk, [&] { return s->stopping || !s->inflight.empty(); });
+        if (s->inflight.empty() && s->stopping)
+            break;
+        Tick t = s->inflight.front();
+        lk.unlock();
+        hipError_t e = hipEventSynchronize(s->tick_done[t.buf]);
+        for (auto *q : t.reqs)
+            if (e == hipSuccess)
+                e = copy_out(q, s->s_d2h);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s->s_d2h);
+        lk.lock();
+        if (s->inflight.empty())     // failed and cleared by another thread
+            continue;
+        s->inflight.pop_front();
+        for (auto *q : t.reqs)
+            finish(s, q, e == hipSuccess ? GK_OK : GK_EDEVICE);
+        s->buf_busy[t.buf] = false;
+        if (e != hipSuccess) {
+            fail_all(s, std::string("server copy out: ") + hipGetErrorName(e));
+            break;
+        }
+        s->cv.notify_all();
+    }
+}
+
+void destroy_server(gk_server *s)
+{
+    DeviceScope dev(s->ctx->device);
+    for (int k = 0; k < 2; ++k) {
+        if (s->graph[k])
+            (void)hipGraphExecDestroy(s->graph[k]);
+        if (s->tick_done[k])
+            (void)hipEventDestroy(s->tick_done[k]);
+        if (s->h_table[k])
+            (void)hipHostFree(s->h_table[k]);
+        if (s->d_table[k])
+            (void)hipFree(s->d_table[k]);
+    }
+    for (auto &kv : s->reqs) {
+        if (kv.second->ready)
+            (void)hipEventDestroy(kv.second->ready);
+        delete kv.second;
+    }
+    if (s->d_arena)
+        (void)hipFree(s->d_arena);
+    if (s->d_counters)
+        (void)hipFree(s->d_counters);
+    if (s->d_resid)
+        (void)hipFree(s->d_resid);
+    for (hipStream_t st : {s->s_copy, s->s_compute, s->s_d2h})
+        if (st)
+            (void)hipStreamDestroy(st);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gk_server_start(gk_ctx *ctx, uint64_t device_budget_bytes, uint32_t max_slots,
+                    uint32_t max_read_len, uint32_t mode, gk_server **out)
+{
+    if (!ctx || !out)
+        return GK_EINVAL;
+    *out = nullptr;
+    if (!ctx->ref_planes)
+        return gk_detail_fail(ctx, GK_ENOREF, "gk_server_start: no reference loaded");
+    if (max_slots < 1 || max_slots > gkd::MAX_TABLE_BATCHES)
+        return gk_detail_fail(ctx, GK_EINVAL, "gk_server_start: max_slots must be 1..256");
+    if (max_read_len < 1 || max_read_len > GK_MAX_READ_LEN)
+        return gk_detail_fail(ctx, GK_EINVAL, "gk_server_start: max_read_len must be 1..512");
+    if (mode != GK_SERVER_BATCHED && mode != GK_SERVER_SEQUENTIAL)
+        return gk_detail_fail(ctx, GK_EINVAL, "gk_server_start: unknown mode");
+    if (device_budget_bytes < (1u << 20))
+        return gk_detail_fail(ctx, GK_EINVAL, "gk_server_start: budget below 1 MiB");
+    DeviceScope dev(ctx->device);
+    gk_server *s = new (std::nothrow) gk_server();
+    if (!s)
+        return gk_detail_fail(ctx, GK_ENOMEM, "gk_server_start: out of host memory");
+    s->ctx = ctx;
+    s->mode = mode;
+    s->max_slots = max_slots;
+    s->max_read_len = max_read_len;
+    s->wmax = (max_read_len + 31) / 32;
+    s->budget = device_budget_bytes;
+    s->arena.init(device_budget_bytes);
+    hipError_t e = hipMalloc(&s->d_arena, device_budget_bytes);
+    for (hipStream_t *st : {&s->s_copy, &s->s_compute, &s->s_d2h})
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipMalloc(&s->d_counters, 2 * sizeof(uint32_t));
+    // Every pair takes at least 11 arena bytes, which bounds a tick's pairs.
+    const uint64_t resid_cap = device_budget_bytes / 11 + 1;
+    if (e == hipSuccess)
+        e = hipMalloc(&s->d_resid, resid_cap * sizeof(uint32_t));
+    if (e == hipSuccess && mode == GK_SERVER_BATCHED) {
+        int per_cu = 0;
+        e = gkd::mixed_blocks_per_cu(s->wmax, GK_READS_SPLIT, 2048, 1, &per_cu);
+        s->margs.table = nullptr;
+        s->margs.tile_counter = s->d_counters;
+        s->margs.resid_count = s->d_counters + 1;
+        s->margs.resid_list = s->d_resid;
+        s->margs.n_tiles = 0;
+        s->margs.tile = 2048;
+        s->margs.ppl = 1;
+        s->margs.sort_e = 1;
+        s->margs.blocks = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)ctx->cu_count;
+        s->margs.resid_blocks = 2u * (uint32_t)ctx->cu_count;
+        hipStream_t cap = nullptr;
+        if (e == hipSuccess)
+            e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            e = hipHostMalloc(&s->h_table[k], sizeof(gkd::BatchTable), hipHostMallocDefault);
+            if (e == hipSuccess)
+                e = hipMalloc(&s->d_table[k], sizeof(gkd::BatchTable));
+            if (e == hipSuccess)
+                e = hipEventCreateWithFlags(&s->tick_done[k], hipEventDisableTiming);
+            if (e != hipSuccess)
+                break;
+            std::memset(s->h_table[k], 0, sizeof(gkd::BatchTable));
+            // Tick graph: table copy, reset, persistent kernel, residual pass.
+            gkd::MixedArgs x = s->margs;
+            x.table = s->d_table[k];
+            hipGraph_t g = nullptr;
+            e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+            if (e != hipSuccess)
+                break;
+            hipError_t le = hipMemcpyAsync(s->d_table[k], s->h_table[k], sizeof(gkd::BatchTable),
+                                           hipMemcpyHostToDevice, cap);
+            if (le == hipSuccess)
+                le = gkd::launch_mixed_table(x, s->wmax, GK_READS_SPLIT, cap);
+            e = hipStreamEndCapture(cap, &g);
+            if (le != hipSuccess)
+                e = le;
+            if (e == hipSuccess)
+                e = hipGraphInstantiate(&s->graph[k], g, nullptr, nullptr, 0);
+            if (g)
+                (void)hipGraphDestroy(g);
+        }
+        if (cap)
+            (void)hipStreamDestroy(cap);
+    }
+    if (e != hipSuccess) {
+        const int code = e == hipErrorOutOfMemory ? GK_ENOMEM : GK_EDEVICE;
+        destroy_server(s);
+        return gk_detail_fail(ctx, code,
+                              std::string("gk_server_start: ") + hipGetErrorName(e));
+    }
+    s->loader = std::thread(loader_main, s);
+    if (mode == GK_SERVER_BATCHED) {
+        s->scheduler = std::thread(scheduler_main, s);
+        s->completer = std::thread(completer_main, s);
+    }
+    *out = s;
+    return GK_OK;
+}
+
+int gk_server_submit(gk_server *s, const gk_request *r, uint64_t *ticket)
+{
+    if (!s || !r || !ticket)
+        return GK_EINVAL;
+    if (r->n_reads == 0 && r->n_pairs > 0)
+        return GK_EINVAL;
+    if (r->n_reads >= (1u << 30) || r->n_pairs >= (1ull << 30) || r->e > 255)
+        return GK_EINVAL;
+    if ((r->n_reads && (!r->reads || !r->read_off)) ||
+        (r->n_pairs && (!r->cand_pos || !r->accept || !r->est)))
+        return GK_EINVAL;
+    Req *q = new (std::nothrow) Req();
+    if (!q)
+        return GK_ENOMEM;
+    q->r = *r;
+    q->t_submit = r->t_arrival_us ? r->t_arrival_us : now_us();
+    if (r->n_reads)
+        plan(q);
+    if (q->max_len > s->max_read_len) {
+        delete q;
+        return GK_ERANGE;
+    }
+    if (q->footprint > s->budget) {
+        delete q;
+        return GK_ERANGE;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) {
+        delete q;
+        return GK_EDEVICE;
+    }
+    if (hipEventCreateWithFlags(&q->ready, hipEventDisableTiming) != hipSuccess) {
+        delete q;
+        return GK_EDEVICE;
+    }
+    q->ticket = s->next_ticket++;
+    s->reqs[q->ticket] = q;
+    if (r->n_pairs == 0) {
+        finish(s, q, GK_OK);
+    } else {
+        s->pending.push_back(q);
+        s->cv.notify_all();
+    }
+    *ticket = q->ticket;
+    return GK_OK;
+}
+
+int gk_server_wait(gk_server *s, uint64_t ticket, int64_t timeout_us, gk_request_stats *stats)
+{
+    if (!s)
+        return GK_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end())
+        return GK_EINVAL;
+    Req *q = it->second;
+    auto done = [&] { return q->done; };
+    if (timeout_us < 0) {
+        s->cv.wait(lk, done);
+    } else if (!s->cv.wait_for(lk, std::chrono::microseconds(timeout_us), done)) {
+        return GK_ETIMEOUT;
+    }
+    if (stats) {
+        stats->status = q->status;
+        stats->n_pairs = q->r.n_pairs;
+        stats->t_submit_us = q->t_submit;
+        stats->t_admit_us = q->t_admit;
+        stats->t_done_us = q->t_done;
+    }
+    const int st = q->status;
+    s->reqs.erase(it);
+    lk.unlock();
+    if (q->ready) {
+        DeviceScope dev(s->ctx->device);
+        (void)hipEventDestroy(q->ready);
+    }
+    delete q;
+    return st;
+}
+
+int gk_server_counters(gk_server *s, uint64_t *ticks, uint64_t *max_requests_per_tick,
+                       uint64_t *pairs_done)
+{
+    if (!s)
+        return GK_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (ticks)
+        *ticks = s->ticks;
+    if (max_requests_per_tick)
+        *max_requests_per_tick = s->tick_req_max;
+    if (pairs_done)
+        *pairs_done = s->pairs_done;
+    return GK_OK;
+}
+
+int gk_server_stop(gk_server *s)
+{
+    if (!s)
+        return GK_EINVAL;
+    {
+        // Let the work already submitted finish, then stop the threads.
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv.wait(lk, [&] {
+            return s->stopping ||
+                   (s->pending.empty() && s->ready.empty() && s->inflight.empty() &&
+                    s->slots_used == 0);
+        });
+        s->stopping = true;
+        for (auto *q : s->pending)
+            finish(s, q, GK_EDEVICE);
+        s->pending.clear();
+        s->cv.notify_all();
+    }
+    if (s->loader.joinable())
+        s->loader.join();
+    if (s->scheduler.joinable())
+        s->scheduler.join();
+    if (s->completer.joinable())
+        s->completer.join();
+    const int st = s->err.empty() ? GK_OK : GK_EDEVICE;
+    destroy_server(s);
+    return st;
+}
+
+int64_t gk_clock_us(void) { return now_us(); }
+
+}  // extern "C"

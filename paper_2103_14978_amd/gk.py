@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgk.so")
 
 GK_OK, GK_EINVAL, GK_ENOMEM, GK_EDEVICE, GK_ENOREF, GK_ERANGE = 0, -1, -2, -3, -4, -5
+GK_ETIMEOUT = -7
+GK_SERVER_BATCHED, GK_SERVER_SEQUENTIAL = 0, 1
 GK_REJECT, GK_ACCEPT, GK_UNDEFINED, GK_INVALID = 0, 1, 2, 3
 GK_EST_NONE = 0xFFFF
 GK_MAX_READ_LEN = 512
@@ -27,7 +29,7 @@ GK_OPT_MIXED_SORT_E = 4
 GK_OPT_MIXED_BLOCKS_PER_CU = 5
 GK_OPT_MIXED_GRAPH = 6
 STATUS_NAMES = {0: "GK_OK", -1: "GK_EINVAL", -2: "GK_ENOMEM", -3: "GK_EDEVICE",
-                -4: "GK_ENOREF", -5: "GK_ERANGE"}
+                -4: "GK_ENOREF", -5: "GK_ERANGE", -7: "GK_ETIMEOUT"}
 
 
 class GkError(RuntimeError):
@@ -53,6 +55,31 @@ class gk_batch(ctypes.Structure):
         ("accept", ctypes.c_void_p),
         ("est", ctypes.c_void_p),
         ("accept_bits", ctypes.c_void_p),
+    ]
+
+
+class gk_request(ctypes.Structure):
+    _fields_ = [
+        ("reads", ctypes.c_void_p),
+        ("read_off", ctypes.c_void_p),
+        ("n_reads", ctypes.c_uint32),
+        ("e", ctypes.c_uint32),
+        ("pair_read", ctypes.c_void_p),
+        ("cand_pos", ctypes.c_void_p),
+        ("n_pairs", ctypes.c_uint64),
+        ("accept", ctypes.c_void_p),
+        ("est", ctypes.c_void_p),
+        ("t_arrival_us", ctypes.c_int64),
+    ]
+
+
+class gk_request_stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("n_pairs", ctypes.c_uint64),
+        ("t_submit_us", ctypes.c_int64),
+        ("t_admit_us", ctypes.c_int64),
+        ("t_done_us", ctypes.c_int64),
     ]
 
 
@@ -87,6 +114,19 @@ def lib() -> ctypes.CDLL:
         L.gk_tune_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp, u64, ctypes.c_char_p,
                                     ctypes.c_char_p, ctypes.c_size_t]
         L.gk_tune_mixed.restype = i32
+        L.gk_server_start.argtypes = [vp, u64, u32, u32, u32, ctypes.POINTER(vp)]
+        L.gk_server_start.restype = i32
+        L.gk_server_submit.argtypes = [vp, ctypes.POINTER(gk_request), ctypes.POINTER(u64)]
+        L.gk_server_submit.restype = i32
+        L.gk_server_wait.argtypes = [vp, u64, ctypes.c_int64, ctypes.POINTER(gk_request_stats)]
+        L.gk_server_wait.restype = i32
+        L.gk_server_counters.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                         ctypes.POINTER(u64)]
+        L.gk_server_counters.restype = i32
+        L.gk_server_stop.argtypes = [vp]
+        L.gk_server_stop.restype = i32
+        L.gk_clock_us.argtypes = []
+        L.gk_clock_us.restype = ctypes.c_int64
         L.gk_set_option.argtypes = [vp, i32, ctypes.c_int64]
         L.gk_set_option.restype = i32
         L.gk_get_option.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_int64)]
@@ -97,7 +137,9 @@ def lib() -> ctypes.CDLL:
 
 EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
             "gk_reference_info", "gk_encode_reads", "gk_filter", "gk_set_option",
-            "gk_get_option", "gk_filter_mixed", "gk_tune_mixed")
+            "gk_get_option", "gk_filter_mixed", "gk_tune_mixed", "gk_server_start",
+            "gk_server_submit", "gk_server_wait", "gk_server_counters", "gk_server_stop",
+            "gk_clock_us")
 
 
 def ptr(x) -> int | None:
@@ -216,3 +258,74 @@ def gk_tune_mixed(ctx, batch: gk_batch, stream=None, sample_pairs: int = 0,
                              cache_path.encode() if cache_path else None, buf, report_cap)
     _check(ctx, st, "gk_tune_mixed")
     return buf.value.decode()
+
+
+# ------------------------------------------------------------------ serving ---
+
+def gk_server_start(ctx, device_budget_bytes: int, max_slots: int, max_read_len: int,
+                    mode: int = GK_SERVER_BATCHED) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(ctx, lib().gk_server_start(ctx, device_budget_bytes, max_slots, max_read_len, mode,
+                                      ctypes.byref(h)), "gk_server_start")
+    return h
+
+
+class Request:
+    """A gk_request over host numpy arrays, which it keeps alive, with its own
+    output arrays (accept uint8, est uint16)."""
+
+    def __init__(self, reads, read_off, cand_pos, e: int, pair_read=None, t_arrival_us: int = 0):
+        import numpy as np
+        self.reads = np.ascontiguousarray(reads, dtype=np.uint8)
+        self.read_off = np.ascontiguousarray(read_off, dtype=np.uint64)
+        self.cand_pos = np.ascontiguousarray(cand_pos, dtype=np.uint32)
+        self.pair_read = (np.ascontiguousarray(pair_read, dtype=np.uint32)
+                          if pair_read is not None else None)
+        n = len(self.cand_pos)
+        self.accept = np.zeros(n, dtype=np.uint8)
+        self.est = np.zeros(n, dtype=np.uint16)
+        r = gk_request()
+        r.reads = self.reads.ctypes.data if self.reads.size else None
+        r.read_off = self.read_off.ctypes.data
+        r.n_reads = len(self.read_off) - 1
+        r.e = e
+        r.pair_read = self.pair_read.ctypes.data if self.pair_read is not None else None
+        r.cand_pos = self.cand_pos.ctypes.data if n else None
+        r.n_pairs = n
+        r.accept = self.accept.ctypes.data if n else None
+        r.est = self.est.ctypes.data if n else None
+        r.t_arrival_us = t_arrival_us
+        self.struct = r
+
+
+def gk_server_submit(srv, req: Request) -> int:
+    t = ctypes.c_uint64()
+    st = lib().gk_server_submit(srv, ctypes.byref(req.struct), ctypes.byref(t))
+    if st != GK_OK:
+        raise GkError(st, "gk_server_submit")
+    return int(t.value)
+
+
+def gk_server_wait(srv, ticket: int, timeout_us: int = -1):
+    """(status, gk_request_stats); status GK_ETIMEOUT leaves the ticket queued."""
+    s = gk_request_stats()
+    st = lib().gk_server_wait(srv, ticket, timeout_us, ctypes.byref(s))
+    return int(st), s
+
+
+def gk_server_counters(srv) -> tuple[int, int, int]:
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    st = lib().gk_server_counters(srv, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+    if st != GK_OK:
+        raise GkError(st, "gk_server_counters")
+    return int(a.value), int(b.value), int(c.value)
+
+
+def gk_server_stop(srv) -> None:
+    st = lib().gk_server_stop(srv)
+    if st != GK_OK:
+        raise GkError(st, "gk_server_stop")
+
+
+def gk_clock_us() -> int:
+    return int(lib().gk_clock_us())
