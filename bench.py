@@ -86,10 +86,19 @@ def main() -> int:
                     help="run one plain 256 MiB device copy kernel first (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the CPU-baseline sample")
-    ap.add_argument("--workload", choices=["plain", "mixed"], default="plain",
+    ap.add_argument("--workload", choices=["plain", "mixed", "served"], default="plain",
                     help="plain: 100 bp, e=5 (the headline); mixed: 2^26 pairs of mixed "
                          "lengths and per-pair e, persistent launch vs one launch per "
-                         "(length, e) group")
+                         "(length, e) group; served: Poisson request stream over a 3.1 Gbp "
+                         "reference, batched server vs sequential per-request launches")
+    ap.add_argument("--lambdas", default="50,100,200,500,1000,2000,3000,4000,6000,8000",
+                    help="served: arrival rates (requests/s)")
+    ap.add_argument("--duration", type=float, default=6.0,
+                    help="served: seconds of arrivals per rate and mode")
+    ap.add_argument("--pool", type=int, default=256, help="served: distinct requests")
+    ap.add_argument("--ref-len", type=int, default=3_100_000_000,
+                    help="served: reference length")
+    ap.add_argument("--slo-ms", type=float, default=25.0, help="served: p99 target")
     ap.add_argument("--tune-sample", type=int, default=1 << 21,
                     help="mixed: pairs the autotuner times each candidate on")
     args = ap.parse_args()
@@ -117,6 +126,8 @@ def main() -> int:
 
     if args.workload == "mixed":
         return bench_mixed(args, log)
+    if args.workload == "served":
+        return bench_served(args, log)
 
     t = time.time()
     ref = gen.c1_reference()
@@ -351,6 +362,145 @@ def bench_mixed(args, log) -> int:
                      "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
                      "ops_per_pair_mean": round(ops / n_pairs, 1)},
         "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    gk.gk_destroy(ctx)
+    return 0
+
+
+def bench_served(args, log) -> int:
+    """Served form: a device-resident 3.1 Gbp reference; requests of 10^3 to
+    10^6 pairs (log-uniform), each with one read length in 100..250 and its own
+    e; open-loop Poisson arrivals.  Latency = results in host memory minus the
+    scheduled arrival time, so queueing counts.  The batched server against
+    the sequential per-request form (copy in, launch, copy out, one request at
+    a time on one stream)."""
+    import threading
+    import torch
+    import gen
+    from paper_2103_14978_amd import gk
+
+    t = time.time()
+    ref = gen.c4_reference(args.ref_len)
+    log(f"reference {len(ref)} bp generated in {time.time() - t:.1f}s")
+    ctx = gk.gk_create(0)
+    t = time.time()
+    gk.gk_load_reference(ctx, ref)
+    log(f"reference resident in {time.time() - t:.1f}s")
+    t = time.time()
+    pool = [gen.c4_request(ref, k) for k in range(args.pool)]
+    pool_pairs = np.array([ps.n_pairs for ps in pool], dtype=np.float64)
+    log(f"{len(pool)} requests generated in {time.time() - t:.1f}s, mean "
+        f"{pool_pairs.mean():.0f} pairs")
+    # Oracle outputs of a few pool requests: every submission of them is checked.
+    import oracle
+    checked = {}
+    for k in range(min(8, len(pool))):
+        ps = pool[k]
+        checked[k] = oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read, ps.cand_pos,
+                                         ps.meta["e"], n_threads=gen.default_threads())
+    budget = 8 << 30
+    rates = [float(x) for x in args.lambdas.split(",")]
+    results = {}
+    mismatches = 0
+    for mode_name, mode in (("served", gk.GK_SERVER_BATCHED),
+                            ("per_request", gk.GK_SERVER_SEQUENTIAL)):
+        results[mode_name] = []
+        saturated = False
+        for lam in rates:
+            if saturated:
+                results[mode_name].append({"lambda": lam, "skipped": "saturated at a lower rate"})
+                continue
+            srv = gk.gk_server_start(ctx, budget, 128, 256, mode)
+            rng = np.random.default_rng(int(lam) * 7 + mode)
+            n_req = max(20, int(lam * args.duration))
+            gaps = rng.exponential(1.0 / lam, n_req)
+            which = rng.integers(0, len(pool), n_req)
+            tickets = []
+            reqs = []
+            done = []
+            t0 = gk.gk_clock_us() + 200_000
+            arrivals = t0 + (np.cumsum(gaps) * 1e6).astype(np.int64)
+
+            def submit():
+                for k in range(n_req):
+                    while True:
+                        d = arrivals[k] - gk.gk_clock_us()
+                        if d <= 0:
+                            break
+                        time.sleep(min(d, 2000) / 1e6)
+                    ps = pool[which[k]]
+                    r = gk.Request(ps.reads, ps.read_off, ps.cand_pos, ps.meta["e"],
+                                   pair_read=ps.pair_read, t_arrival_us=int(arrivals[k]))
+                    reqs.append(r)
+                    tickets.append(gk.gk_server_submit(srv, r))
+
+            th = threading.Thread(target=submit)
+            th.start()
+            deadline = t0 + int((args.duration + 20) * 1e6)
+            k = 0
+            while k < n_req:
+                if k >= len(tickets):
+                    time.sleep(0.0005)
+                    continue
+                left = deadline - gk.gk_clock_us()
+                if left <= 0:
+                    break
+                st, stats = gk.gk_server_wait(srv, tickets[k], left)
+                if st == gk.GK_ETIMEOUT:
+                    break
+                done.append((stats.t_done_us - stats.t_submit_us, stats.n_pairs))
+                w = int(which[k])
+                if w in checked:
+                    ra, rs = checked[w]
+                    mismatches += int(np.sum((reqs[k].accept != ra) | (reqs[k].est != rs)))
+                reqs[k] = None                 # release its output buffers
+                k += 1
+            th.join()
+            # requests still unfinished at the deadline count as missing the SLO
+            unfinished = n_req - len(done)
+            saturated = unfinished > 0
+            ticks, per_tick, _ = gk.gk_server_counters(srv)
+            gk.gk_server_stop(srv)
+            lat = np.array([d for d, _ in done], dtype=np.float64) / 1e3
+            lat_all = np.concatenate([lat, np.full(unfinished, np.inf)])
+            span = (max(arrivals[-1], gk.gk_clock_us()) - t0) / 1e6
+            def pct(q):
+                v = float(np.percentile(lat_all, q))
+                return round(v, 3) if np.isfinite(v) else None
+            rec = {"lambda": lam, "requests": n_req, "unfinished": unfinished,
+                   "p50_ms": pct(50), "p99_ms": pct(99), "p999_ms": pct(99.9),
+                   "max_ms": round(float(lat.max()), 3) if len(lat) else None,
+                   "pairs_per_s": round(float(sum(n for _, n in done)) / span, 1),
+                   "ticks": ticks, "max_requests_per_tick": per_tick}
+            results[mode_name].append(rec)
+            log(f"{mode_name} lambda={lam}: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms, "
+                f"{rec['pairs_per_s'] / 1e6:.1f} M pairs/s, unfinished {unfinished}")
+
+    def at_slo(rows):
+        ok = [r for r in rows if r["p99_ms"] is not None and r["p99_ms"] <= args.slo_ms
+              and r["unfinished"] == 0]
+        if not ok:
+            return None
+        best = max(ok, key=lambda r: r["lambda"])
+        return {"lambda": best["lambda"], "pairs_per_s": best["pairs_per_s"],
+                "p99_ms": best["p99_ms"]}
+
+    served_slo, seq_slo = at_slo(results["served"]), at_slo(results["per_request"])
+    out = {
+        "metric": "p99 request latency and pairs/sec at p99 <= SLO, served filter, 1 MI355X, "
+                  "bit-exact",
+        "value": served_slo["pairs_per_s"] if served_slo else None, "unit": "pairs/s",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "u32",
+        "vs_baseline": None,
+        "config": {"workload": f"served: {len(ref)} bp GC-41% reference resident, pool of "
+                               f"{len(pool)} requests of 1e3..1e6 pairs (log-uniform, mean "
+                               f"{pool_pairs.mean():.0f}), read length U{{100..250}}, own e "
+                               "U{0..floor(0.1 m)}, open-loop Poisson arrivals, "
+                               f"{args.duration:.0f} s per rate", "slo_p99_ms": args.slo_ms},
+        "served_at_slo": served_slo, "per_request_at_slo": seq_slo,
+        "by_rate": results, "parity": {"checked_pool_requests": len(checked),
+                                       "mismatches": mismatches},
     }
     print(json.dumps(out), flush=True)
     gk.gk_destroy(ctx)

@@ -44,6 +44,8 @@ extern "C" {
 #define GK_ENOREF   (-4)   /* no reference loaded                            */
 #define GK_ERANGE   (-5)   /* size beyond a documented limit                 */
 #define GK_ETIMEOUT (-7)   /* gk_server_wait: not finished within the timeout */
+#define GK_ECANCELED (-8)  /* request cancelled by gk_server_stop before it
+                              was admitted                                   */
 
 /* Per-pair result codes written to gk_batch.accept. */
 #define GK_REJECT     0u   /* edit estimate > e                              */
@@ -270,7 +272,8 @@ typedef struct gk_request {
 } gk_request;
 
 typedef struct gk_request_stats {
-    int     status;                /* GK_OK, or GK_EDEVICE if the server failed */
+    int     status;                /* GK_OK; GK_ECANCELED (stopped before
+                                      admission); GK_EDEVICE (server failed) */
     uint64_t n_pairs;
     int64_t t_submit_us;           /* arrival time (t_arrival_us or submit)  */
     int64_t t_admit_us;            /* admitted to a slot                     */
@@ -300,7 +303,9 @@ int gk_server_wait(gk_server *srv, uint64_t ticket, int64_t timeout_us,
 int gk_server_counters(gk_server *srv, uint64_t *ticks, uint64_t *max_requests_per_tick,
                        uint64_t *pairs_done);
 
-/* Finish every submitted request, stop the threads, free the server. */
+/* Cancel the requests not yet admitted (their status: GK_ECANCELED), finish
+   the admitted ones, stop the threads and free the server.  Tickets not yet
+   waited for are released. */
 int gk_server_stop(gk_server *srv);
 
 /* The clock of gk_request.t_arrival_us and gk_request_stats: microseconds of

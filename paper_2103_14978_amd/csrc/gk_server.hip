@@ -296,13 +296,23 @@ void loader_main(gk_server *s)
             break;
         Req *q = s->pending.front();
         uint64_t off = 0;
-        // Admission in arrival order: wait for a slot and arena room.
+        bool got = false;
+        // Admission in arrival order: wait for a slot and arena room.  The
+        // head may be cancelled meanwhile (gk_server_stop): then start over.
         s->cv.wait(lk, [&] {
-            return s->stopping ||
-                   (s->slots_used < s->max_slots && s->arena.alloc(q->footprint, &off));
+            if (s->stopping || s->pending.empty() || s->pending.front() != q)
+                return true;
+            if (s->slots_used < s->max_slots && s->arena.alloc(q->footprint, &off))
+                got = true;
+            return got;
         });
-        if (s->stopping)
+        if (s->stopping) {
+            if (got)
+                s->arena.release(off, q->footprint);
             break;
+        }
+        if (!got)
+            continue;
         s->pending.pop_front();
         s->slots_used++;
         q->admitted = true;
@@ -667,17 +677,17 @@ int gk_server_stop(gk_server *s)
     if (!s)
         return GK_EINVAL;
     {
-        // Let the work already submitted finish, then stop the threads.
+        // Requests not admitted yet are cancelled; admitted ones finish.
         std::unique_lock<std::mutex> lk(s->mu);
+        for (auto *q : s->pending)
+            finish(s, q, GK_ECANCELED);
+        s->pending.clear();
+        s->cv.notify_all();
         s->cv.wait(lk, [&] {
             return s->stopping ||
-                   (s->pending.empty() && s->ready.empty() && s->inflight.empty() &&
-                    s->slots_used == 0);
+                   (s->ready.empty() && s->inflight.empty() && s->slots_used == 0);
         });
         s->stopping = true;
-        for (auto *q : s->pending)
-            finish(s, q, GK_EDEVICE);
-        s->pending.clear();
         s->cv.notify_all();
     }
     if (s->loader.joinable())

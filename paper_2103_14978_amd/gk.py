@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgk.so")
 
 GK_OK, GK_EINVAL, GK_ENOMEM, GK_EDEVICE, GK_ENOREF, GK_ERANGE = 0, -1, -2, -3, -4, -5
 GK_ETIMEOUT = -7
+GK_ECANCELED = -8
 GK_SERVER_BATCHED, GK_SERVER_SEQUENTIAL = 0, 1
 GK_REJECT, GK_ACCEPT, GK_UNDEFINED, GK_INVALID = 0, 1, 2, 3
 GK_EST_NONE = 0xFFFF
@@ -29,7 +30,7 @@ GK_OPT_MIXED_SORT_E = 4
 GK_OPT_MIXED_BLOCKS_PER_CU = 5
 GK_OPT_MIXED_GRAPH = 6
 STATUS_NAMES = {0: "GK_OK", -1: "GK_EINVAL", -2: "GK_ENOMEM", -3: "GK_EDEVICE",
-                -4: "GK_ENOREF", -5: "GK_ERANGE", -7: "GK_ETIMEOUT"}
+                -4: "GK_ENOREF", -5: "GK_ERANGE", -7: "GK_ETIMEOUT", -8: "GK_ECANCELED"}
 
 
 class GkError(RuntimeError):

@@ -150,3 +150,19 @@ def test_unknown_bases_in_requests(gkctx):
     for k, ((a, s), (ps, e)) in enumerate(zip(outs, reqs)):
         ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, e)
         assert_same(a, s, ra, rs, f"unknown-base request {k}")
+
+
+def test_stop_cancels_unadmitted(gkctx, served):
+    """Stopping a busy sequential server returns once the admitted request is
+    done; requests still queued are cancelled, not run."""
+    import time
+    ref, reqs, want = served
+    gk.gk_load_reference(gkctx, ref)
+    srv = gk.gk_server_start(gkctx, 1 << 30, 4, 256, gk.GK_SERVER_SEQUENTIAL)
+    objs = [gk.Request(ps.reads, ps.read_off, ps.cand_pos, e, pair_read=ps.pair_read)
+            for ps, e in reqs * 5]
+    for o in objs:
+        gk.gk_server_submit(srv, o)
+    t = time.time()
+    gk.gk_server_stop(srv)
+    assert time.time() - t < 30
