@@ -47,18 +47,19 @@ def bytes_per_pair(m: int) -> int:
     return m // 4 + m // 4 + 8 + 3 + 2
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(files=("gk_filter.hip", "gk_pair.h", "gk_internal.h")) -> str:
     h = hashlib.sha256()
-    for f in ("gk_filter.hip", "gk_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2103_14978_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(kernel_hash: str, n_pairs: int):
+def traffic_from_profile(kernel_hash: str, n_pairs: int,
+                         name: str = "k_filter_w4_config1_e5_counters.json"):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on this exact kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "k_filter_w4_config1_e5_counters.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             d = json.load(f)
@@ -99,8 +100,11 @@ def main() -> int:
     ap.add_argument("--ref-len", type=int, default=3_100_000_000,
                     help="served: reference length")
     ap.add_argument("--slo-ms", type=float, default=25.0, help="served: p99 target")
-    ap.add_argument("--tune-sample", type=int, default=1 << 21,
+    ap.add_argument("--tune-sample", type=int, default=1 << 23,
                     help="mixed: pairs the autotuner times each candidate on")
+    ap.add_argument("--mixed-config", default=None,
+                    help="mixed: fixed tuning 'tile,ppl,sort_e,blocks_per_cu' instead of "
+                         "the autotuner")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -295,10 +299,25 @@ def bench_mixed(args, log) -> int:
     torch.cuda.synchronize()
     log(f"{len(groups)} (length, e) groups")
 
+    if args.calibrate_copy:
+        x = torch.ones(64 << 20, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        torch.bitwise_xor(x, 0x55, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        log("copy calibration kernel: 268435456 bytes read, 268435456 bytes written")
     t = time.time()
-    report = json.loads(gk.gk_tune_mixed(ctx, batch, stream, sample_pairs=args.tune_sample))
-    log(f"autotuned in {time.time() - t:.2f}s: tile {report['tile']} ppl {report['ppl']} "
-        f"sort_e {report['sort_e']} blocks/CU {report['blocks_per_cu']}")
+    if args.mixed_config:
+        tile, ppl, sort_e, bpc = (int(v) for v in args.mixed_config.split(","))
+        for opt, val in ((gk.GK_OPT_MIXED_TILE, tile), (gk.GK_OPT_MIXED_PAIRS_PER_LANE, ppl),
+                         (gk.GK_OPT_MIXED_SORT_E, sort_e), (gk.GK_OPT_MIXED_BLOCKS_PER_CU, bpc)):
+            gk.gk_set_option(ctx, opt, val)
+        report = {"tile": tile, "ppl": ppl, "sort_e": sort_e, "blocks_per_cu": bpc,
+                  "ms": None, "source": "fixed"}
+    else:
+        report = json.loads(gk.gk_tune_mixed(ctx, batch, stream, sample_pairs=args.tune_sample))
+    log(f"tuning ({report.get('source')}) in {time.time() - t:.2f}s: tile {report['tile']} "
+        f"ppl {report['ppl']} sort_e {report['sort_e']} blocks/CU {report['blocks_per_cu']}")
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -340,6 +359,8 @@ def bench_mixed(args, log) -> int:
     w = (m_pair + 31) // 32
     ops = int(np.sum(14 * (2 * np.minimum(e_pair, m_pair - 1) + 1) * w + 6 * w + 16))
     achieved = ops / k_m / 1e12
+    mhash = kernel_source_hash(("gk_mixed.hip", "gk_pair.h", "gk_internal.h"))
+    mtraffic = traffic_from_profile(mhash, n_pairs, "k_mixed_w10_config3_counters.json")
     out = {
         "metric": "filtered pairs/sec, mixed batch (lengths 64-300, per-pair e), 1 MI355X, "
                   "bit-exact",
@@ -356,11 +377,12 @@ def bench_mixed(args, log) -> int:
                     "kernel_pairs_per_s": round(n_pairs / k_g, 1),
                     "ms_per_step": round(wall_g * 1e3 / steps, 4)},
         "speedup_vs_grouped": round(wall_g / wall_m, 3),
-        "autotune": {k: report[k] for k in ("tile", "ppl", "sort_e", "blocks_per_cu", "ms")},
+        "autotune": {k: report.get(k) for k in ("source", "tile", "ppl", "sort_e",
+                                                 "blocks_per_cu", "ms")},
         "roofline": {"bound": "alu", "kernel": "k_mixed<10>", "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None,
-                     "ops_per_pair_mean": round(ops / n_pairs, 1)},
+                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": mtraffic,
+                     "ops_per_pair_mean": round(ops / n_pairs, 1), "kernel_source_hash": mhash},
         "parity": parity,
     }
     print(json.dumps(out), flush=True)

@@ -218,7 +218,7 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream);
  * Autotuner for gk_filter_mixed.  Times every candidate tuning (tile 2048 /
  * 4096 / 8192, 1 or 2 pairs per lane, sort by e or not, full or half
  * persistent grid) on the first sample_pairs pairs of the batch (0 = all),
- * median of 3 runs each after a warm-up, and keeps the fastest in the
+ * median of 5 runs each after a warm-up, and keeps the fastest in the
  * context.  The outputs of the sampled pairs are written (correct results:
  * every tuning gives the same ones).  Synchronous.
  *

@@ -258,6 +258,7 @@ int prepare_batch(gk_ctx *ctx, const gk_batch *b, const char *who, gkd::FilterAr
     a.accept = b->accept;
     a.est = b->est;
     a.accept_bits = reinterpret_cast<unsigned long long *>(b->accept_bits);
+    a.stream_reads = b->pair_read == nullptr;
     return GK_OK;
 }
 
@@ -359,6 +360,7 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
         return fail(ctx, GK_EDEVICE, "gk_filter_mixed: hipSetDevice failed");
     if ((st = ensure_mixed_scratch(ctx, b->n_pairs)) != GK_OK)
         return st;
+    a.stream_reads = 0;     // the mixed kernel reads each pair entry twice
     const uint32_t wmax = (b->max_read_len + 31) / 32;
     gkd::MixedArgs x;
     if ((st = mixed_args(ctx, ctx->mixed, wmax, b->read_layout, x)) != GK_OK)
@@ -486,6 +488,7 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_
         return fail(ctx, GK_EDEVICE, "gk_tune_mixed: hipSetDevice failed");
     if ((st = ensure_mixed_scratch(ctx, b->n_pairs)) != GK_OK)
         return st;
+    a.stream_reads = 0;
     const uint32_t wmax = (b->max_read_len + 31) / 32;
     const uint64_t n_full = b->n_pairs;
     if (sample_pairs && sample_pairs < a.n_pairs)
@@ -565,8 +568,8 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_
                         (void)hipEventDestroy(e1);
                         return st;
                     }
-                    float times[3];
-                    for (int rep_i = -1; rep_i < 3 && err == hipSuccess; ++rep_i) {
+                    float times[5];
+                    for (int rep_i = -1; rep_i < 5 && err == hipSuccess; ++rep_i) {
                         err = hipEventRecord(e0, s);
                         if (err == hipSuccess)
                             err = gkd::launch_mixed(a, x, wmax, b->read_layout, s);
@@ -582,8 +585,8 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_
                     }
                     if (err != hipSuccess)
                         break;
-                    std::sort(times, times + 3);
-                    const float med = times[1];
+                    std::sort(times, times + 5);
+                    const float med = times[2];
                     rep << (first ? "" : ", ") << "{\"tile\": " << tile << ", \"ppl\": " << ppl
                         << ", \"sort_e\": " << sort_e << ", \"blocks_per_cu\": " << bpc
                         << ", \"ms\": " << med << "}";

@@ -36,59 +36,70 @@ struct MixedLds {
 };
 
 // Dynamic LDS after MixedLds: keys[T] u16, sorted[T] u16, chunk_start[C] u32,
-// chunk_info[C] u32 with C = T/64 + 16.
+// chunk_info[C] u32 with C = T/64 + 16, then the tile's results out_est[T] u16
+// and out_acc[T] u8, written back to HBM in slot order once the tile is done
+// (results land in sorted order, so writing them directly would scatter
+// partial-line writes).
 __host__ __device__ inline uint32_t mixed_chunk_cap(uint32_t tile) { return tile / 64 + 16; }
 
 __host__ inline size_t mixed_lds_bytes(uint32_t tile)
 {
-    return sizeof(MixedLds) + 2u * tile * sizeof(uint16_t) + 2u * mixed_chunk_cap(tile) * 4u;
+    return sizeof(MixedLds) + 2u * tile * sizeof(uint16_t) + 2u * mixed_chunk_cap(tile) * 4u +
+           3u * tile;
 }
 
+struct TileOut {
+    uint8_t *acc;
+    uint16_t *est;
+};
+
 template <int W, int L>
-__device__ __forceinline__ void run_chunk_pair(const FilterArgs &a, uint32_t i)
+__device__ __forceinline__ void run_chunk_pair(const FilterArgs &a, const TileOut &o,
+                                               uint32_t base, uint32_t slot)
 {
-    const PairIdx p = load_idx(a, i);
+    const PairIdx p = load_idx(a, base + slot);
     PairData<W> d;
     load_data<W>(a, p, d);
     uint32_t est;
     const uint32_t res = compute_pair<W, L, false>(a, p, d, est);
-    __builtin_nontemporal_store((uint8_t)res, a.accept + i);
-    __builtin_nontemporal_store((uint16_t)est, a.est + i);
+    o.acc[slot] = (uint8_t)res;
+    o.est[slot] = (uint16_t)est;
 }
 
 template <int W, int L>
-__device__ __forceinline__ void run_chunk_pair2(const FilterArgs &a, uint32_t i0, bool has1,
-                                                uint32_t i1)
+__device__ __forceinline__ void run_chunk_pair2(const FilterArgs &a, const TileOut &o,
+                                                uint32_t base, uint32_t s0, bool has1,
+                                                uint32_t s1)
 {
     // both pairs' loads in flight before either is computed
-    const PairIdx p0 = load_idx(a, i0);
-    const PairIdx p1 = load_idx(a, has1 ? i1 : i0);
+    const PairIdx p0 = load_idx(a, base + s0);
+    const PairIdx p1 = load_idx(a, base + (has1 ? s1 : s0));
     PairData<W> d0, d1;
     load_data<W>(a, p0, d0);
     load_data<W>(a, p1, d1);
     uint32_t est;
     uint32_t res = compute_pair<W, L, false>(a, p0, d0, est);
-    __builtin_nontemporal_store((uint8_t)res, a.accept + i0);
-    __builtin_nontemporal_store((uint16_t)est, a.est + i0);
+    o.acc[s0] = (uint8_t)res;
+    o.est[s0] = (uint16_t)est;
     if (has1) {
         res = compute_pair<W, L, false>(a, p1, d1, est);
-        __builtin_nontemporal_store((uint8_t)res, a.accept + i1);
-        __builtin_nontemporal_store((uint16_t)est, a.est + i1);
+        o.acc[s1] = (uint8_t)res;
+        o.est[s1] = (uint16_t)est;
     }
 }
 
 template <int WMAX, int L, int PPL>
-__device__ __forceinline__ void run_chunk(const FilterArgs &a, uint32_t w, uint32_t i0, bool has1,
-                                          uint32_t i1)
+__device__ __forceinline__ void run_chunk(const FilterArgs &a, const TileOut &o, uint32_t base,
+                                          uint32_t w, uint32_t s0, bool has1, uint32_t s1)
 {
-#define GK_CASE(N)                                                        \
-    case N:                                                               \
-        if (N <= WMAX) {                                                  \
-            if (PPL == 2)                                                 \
-                run_chunk_pair2<(N <= WMAX ? N : 1), L>(a, i0, has1, i1); \
-            else                                                          \
-                run_chunk_pair<(N <= WMAX ? N : 1), L>(a, i0);            \
-        }                                                                 \
+#define GK_CASE(N)                                                                 \
+    case N:                                                                        \
+        if (N <= WMAX) {                                                           \
+            if (PPL == 2)                                                          \
+                run_chunk_pair2<(N <= WMAX ? N : 1), L>(a, o, base, s0, has1, s1); \
+            else                                                                   \
+                run_chunk_pair<(N <= WMAX ? N : 1), L>(a, o, base, s0);            \
+        }                                                                          \
         break;
     switch (w) {
         GK_CASE(1) GK_CASE(2) GK_CASE(3) GK_CASE(4) GK_CASE(5) GK_CASE(6) GK_CASE(7) GK_CASE(8)
@@ -125,6 +136,9 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
     uint16_t *sorted = keys + x.tile;
     uint32_t *chunk_start = reinterpret_cast<uint32_t *>(sorted + x.tile);
     uint32_t *chunk_info = chunk_start + mixed_chunk_cap(x.tile);
+    TileOut out;
+    out.est = reinterpret_cast<uint16_t *>(chunk_info + mixed_chunk_cap(x.tile));
+    out.acc = reinterpret_cast<uint8_t *>(out.est + x.tile);
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63u;
@@ -158,12 +172,12 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
                 const PairIdx p = load_idx(a, i);
                 const uint32_t m = p.r < a.n_reads ? (uint32_t)a.read_len[p.r] : 0u;
                 if (m == 0u || m > a.max_read_len) {
-                    a.accept[i] = GK_INVALID;
-                    a.est[i] = GK_EST_NONE;
+                    out.acc[j] = GK_INVALID;
+                    out.est[j] = GK_EST_NONE;
                 } else if ((uint64_t)p.pos + m > a.ref_len ||
                            (a.read_has_n && a.read_has_n[p.r])) {
-                    a.accept[i] = GK_UNDEFINED;
-                    a.est[i] = GK_EST_NONE;
+                    out.acc[j] = GK_UNDEFINED;
+                    out.est[j] = GK_EST_NONE;
                 } else {
                     const uint32_t kmax = p.e < m - 1u ? p.e : m - 1u;
                     const uint32_t w = (m + 31u) / 32u;
@@ -255,11 +269,20 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
             const uint32_t cnt = info & 0xFFFFu;
             const uint32_t w = __builtin_amdgcn_readfirstlane(info >> 16);
             if (lane < cnt) {
-                const uint32_t i0 = base + sorted[start + lane];
+                const uint32_t s0 = sorted[start + lane];
                 const bool has1 = lane + 64u < cnt;
-                const uint32_t i1 = has1 ? base + sorted[start + lane + 64u] : i0;
-                run_chunk<WMAX, L, PPL>(a, w, i0, has1, i1);
+                const uint32_t s1 = has1 ? sorted[start + lane + 64u] : s0;
+                run_chunk<WMAX, L, PPL>(a, out, base, w, s0, has1, s1);
             }
+        }
+        __syncthreads();
+
+        // 6. write the tile's results back in slot order (residual pairs'
+        //    slots hold placeholders; the residual pass overwrites them later)
+        const uint32_t live = n - base < x.tile ? n - base : x.tile;
+        for (uint32_t j = tid; j < live; j += 256) {
+            a.accept[base + j] = out.acc[j];
+            a.est[base + j] = out.est[j];
         }
         __syncthreads();
     }

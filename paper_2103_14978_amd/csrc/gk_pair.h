@@ -279,14 +279,21 @@ struct PairData {
     uint2 win[W + 1];
 };
 
-// Pair indices, read words and read lengths are read once per pair: they are
-// loaded non-temporally so that the L2 keeps the reference lines instead.
+// Loads of data that is used once (a.stream_reads: one pair per read, each
+// pair entry read once) are non-temporal, so that the L2 keeps the reference
+// lines; shared reads (several candidates per read) stay cached.
+template <typename T>
+__device__ __forceinline__ T ld_once(const FilterArgs &a, const T *p)
+{
+    return a.stream_reads ? __builtin_nontemporal_load(p) : *p;
+}
+
 __device__ __forceinline__ PairIdx load_idx(const FilterArgs &a, uint32_t i)
 {
     PairIdx p;
-    p.r = a.pair_read ? __builtin_nontemporal_load(a.pair_read + i) : i;
-    p.pos = __builtin_nontemporal_load(a.cand_pos + i);
-    p.e = a.e_pair ? (uint32_t)__builtin_nontemporal_load(a.e_pair + i) : a.e_uniform;
+    p.r = a.pair_read ? ld_once(a, a.pair_read + i) : i;
+    p.pos = ld_once(a, a.cand_pos + i);
+    p.e = a.e_pair ? (uint32_t)ld_once(a, a.e_pair + i) : a.e_uniform;
     return p;
 }
 
@@ -295,11 +302,11 @@ __device__ __forceinline__ void load_data(const FilterArgs &a, const PairIdx &p,
 {
     const uint32_t r = p.r < a.n_reads ? p.r : 0u;
     const uint32_t pos = p.pos < a.ref_len ? p.pos : 0u;
-    d.m = a.n_reads ? (uint32_t)__builtin_nontemporal_load(a.read_len + r) : 0u;
+    d.m = a.n_reads ? (uint32_t)ld_once(a, a.read_len + r) : 0u;
 #pragma unroll
     for (int j = 0; j < 2 * W; ++j) {
         const uint32_t *row = a.reads + (size_t)j * a.pitch;
-        d.words[j] = (a.n_reads && (uint32_t)j < a.rows) ? __builtin_nontemporal_load(row + r) : 0u;
+        d.words[j] = (a.n_reads && (uint32_t)j < a.rows) ? ld_once(a, row + r) : 0u;
     }
     // Only the words a window of up to max_read_len bases can touch.
     const uint2 *src = a.ref_planes + (pos >> 5);

@@ -222,6 +222,7 @@ gkd::FilterArgs args_for(const gk_server *s, const Req *q)
     a.accept = q->d_acc;
     a.est = q->d_est;
     a.accept_bits = nullptr;
+    a.stream_reads = 0;
     return a;
 }
 

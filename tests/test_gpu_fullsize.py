@@ -1,0 +1,117 @@
+"""Parity at the workloads' full sizes, in the launch configurations the
+benchmark times: outputs sampled against the oracle pair by pair, plus
+properties checked on every pair."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+from gpu_cases import assert_same, run_oracle, say
+from paper_2103_14978_amd import device, gk
+
+pytestmark = pytest.mark.gpu
+
+
+def check_properties(a, s, e, m, label):
+    """Every pair of an ACGT-only workload is ACCEPT or REJECT, with
+    est <= m and accept iff est <= e."""
+    assert set(np.unique(a)) <= {0, 1}, label
+    assert np.all(s.astype(np.int64) <= m), label
+    assert np.array_equal(a == 1, s.astype(np.int64) <= e), label
+
+
+def sample_check(ref, ps, a, s, e, k, seed, label):
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(ps.n_pairs, size=min(ps.n_pairs, k), replace=False))
+    ee = e[idx] if isinstance(e, np.ndarray) else e
+    ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read[idx], ps.cand_pos[idx], ee)
+    assert_same(a[idx], s[idx], ra, rs, label)
+
+
+@pytest.fixture(scope="module")
+def ref100m():
+    return gen.c1_reference()
+
+
+def test_config1_full(gkctx, ref100m):
+    """2^24 pairs of 100 bp, e = 5, one candidate per read (pair_read NULL),
+    split layout, automatic grid: the benchmark's launch."""
+    ref = ref100m
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c1_pairs(ref, 5)
+    say("case: config1 full 2^24 e=5")
+    dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=100)
+    dp = device.upload_pairs(None, ps.cand_pos)
+    gk.gk_filter(gkctx, device.batch_for(dr, dp, e_uniform=5, max_read_len=100), None)
+    torch.cuda.synchronize()
+    a, s = device.results(dp)
+    check_properties(a, s, 5, 100, "config1")
+    sample_check(ref, ps, a, s, 5, 1 << 15, 1, "config1 sample")
+
+
+@pytest.mark.parametrize("m,es", [(150, (3, 7, 15)), (250, (5, 12, 25))])
+def test_config2_full(gkctx, ref100m, m, es):
+    """2^25 pairs at each (read length, e), several candidates per read."""
+    ref = ref100m
+    gk.gk_load_reference(gkctx, ref)
+    for e in es:
+        ps = gen.c2_pairs(ref, m, e)
+        say(f"case: config2 full m={m} e={e} pairs={ps.n_pairs}")
+        dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=m)
+        dp = device.upload_pairs(ps.pair_read, ps.cand_pos)
+        gk.gk_filter(gkctx, device.batch_for(dr, dp, e_uniform=e, max_read_len=m), None)
+        torch.cuda.synchronize()
+        a, s = device.results(dp)
+        check_properties(a, s, e, m, f"config2 m={m} e={e}")
+        sample_check(ref, ps, a, s, e, 1 << 13, e, f"config2 m={m} e={e}")
+        del dr, dp
+
+
+def test_config3_full(gkctx, ref100m):
+    """2^26 mixed pairs: the autotuned persistent launch from its graph equals
+    the plain launch on every pair and the oracle on a sample."""
+    ref = ref100m
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c3_pairs(ref)
+    say(f"case: config3 full pairs={ps.n_pairs}")
+    dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=300)
+    dp = device.upload_pairs(ps.pair_read, ps.cand_pos, ps.e)
+    b = device.batch_for(dr, dp, max_read_len=300)
+    gk.gk_tune_mixed(gkctx, b, None, sample_pairs=1 << 21)
+    gk.gk_filter_mixed(gkctx, b, None)
+    gk.gk_filter_mixed(gkctx, b, None)             # a graph replay
+    torch.cuda.synchronize()
+    a, s = device.results(dp)
+    m = ps.read_len[ps.pair_read].astype(np.int64)
+    check_properties(a, s, ps.e.astype(np.int64), m, "config3")
+    dp2 = device.upload_pairs(ps.pair_read, ps.cand_pos, ps.e)
+    gk.gk_filter(gkctx, device.batch_for(dr, dp2, max_read_len=300), None)
+    torch.cuda.synchronize()
+    a2, s2 = device.results(dp2)
+    assert_same(a, s, a2, s2, "config3 mixed vs plain")
+    sample_check(ref, ps, a, s, ps.e, 1 << 15, 3, "config3 sample")
+    for opt, val in ((gk.GK_OPT_MIXED_TILE, 4096), (gk.GK_OPT_MIXED_PAIRS_PER_LANE, 1),
+                     (gk.GK_OPT_MIXED_SORT_E, 1), (gk.GK_OPT_MIXED_BLOCKS_PER_CU, 0)):
+        gk.gk_set_option(gkctx, opt, val)
+
+
+def test_config4_full(gkctx):
+    """3.1 Gbp resident reference; 16 requests of the served pool through the
+    batched server, every pair against the oracle."""
+    ref = gen.c4_reference()
+    gk.gk_load_reference(gkctx, ref)
+    reqs = [gen.c4_request(ref, k) for k in range(16)]
+    say(f"case: config4 full, {sum(p.n_pairs for p in reqs)} pairs in 16 requests")
+    srv = gk.gk_server_start(gkctx, 8 << 30, 64, 256, gk.GK_SERVER_BATCHED)
+    try:
+        objs = [gk.Request(p.reads, p.read_off, p.cand_pos, p.meta["e"], pair_read=p.pair_read)
+                for p in reqs]
+        tickets = [gk.gk_server_submit(srv, o) for o in objs]
+        for t in tickets:
+            st, _ = gk.gk_server_wait(srv, t, 120_000_000)
+            assert st == gk.GK_OK
+    finally:
+        gk.gk_server_stop(srv)
+    for k, (p, o) in enumerate(zip(reqs, objs)):
+        ra, rs = run_oracle(ref, p.reads, p.read_off, p.pair_read, p.cand_pos, p.meta["e"])
+        assert_same(o.accept, o.est, ra, rs, f"config4 request {k}")
