@@ -56,9 +56,11 @@ def kernel_source_hash(files=("gk_filter.hip", "gk_pair.h", "gk_internal.h")) ->
 
 
 def traffic_from_profile(kernel_hash: str, n_pairs: int,
-                         name: str = "k_filter_w4_config1_e5_counters.json"):
+                         name: str = "k_filter_w4_config1_e5_counters.json", kernel=None,
+                         tuning=None):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on this exact kernel source; else None."""
+    taken on this exact kernel source, batch size, kernel and tuning; else
+    None."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
@@ -67,7 +69,19 @@ def traffic_from_profile(kernel_hash: str, n_pairs: int,
         return None
     if d.get("kernel_source_hash") != kernel_hash or d.get("n_pairs") != n_pairs:
         return None
+    if kernel is not None and not d.get("kernel", "").startswith(kernel):
+        return None
+    if tuning is not None and d.get("tuning") != tuning:
+        return None
     return d.get("hbm_bytes_per_launch")
+
+
+def plain_kernel_name(words: int, e: int, pairs_per_lane: int) -> str:
+    """The plain launch's kernel for this shape: the library takes one pair per
+    lane when (2e+1)*W < 60 under the automatic setting (0)."""
+    if pairs_per_lane == 0:
+        pairs_per_lane = 4 if (2 * e + 1) * words >= 60 else 1
+    return f"k_filter_single<{words}" if pairs_per_lane == 1 else f"k_filter<{words}"
 
 
 def main() -> int:
@@ -80,7 +94,8 @@ def main() -> int:
     ap.add_argument("--layout", choices=["split", "interleaved"], default="split",
                     help="2-bit read layout in HBM (both are 16 bases per 32-bit word)")
     ap.add_argument("--pairs-per-lane", type=int, default=0,
-                    help="plain filter grid shape (0: one device residency)")
+                    help="plain filter grid shape (0: automatic; 1: one pair per lane; "
+                         "65536: one device residency)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -202,8 +217,9 @@ def main() -> int:
     ops = ops_per_pair(m, e) * n_pairs
     achieved_tops = ops / k_avg_s / 1e12
     khash = kernel_source_hash()
-    traffic = traffic_from_profile(khash, n_pairs)
-    roofline = {"bound": "alu", "kernel": "k_filter<4>", "achieved": round(achieved_tops, 3),
+    kname = plain_kernel_name((m + 31) // 32, e, args.pairs_per_lane)
+    traffic = traffic_from_profile(khash, n_pairs, kernel=kname)
+    roofline = {"bound": "alu", "kernel": kname + ">", "achieved": round(achieved_tops, 3),
                 "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
                 "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
                 "ops_per_pair": ops_per_pair(m, e), "kernel_ms": round(k_avg_s * 1e3, 4),
@@ -360,7 +376,9 @@ def bench_mixed(args, log) -> int:
     ops = int(np.sum(14 * (2 * np.minimum(e_pair, m_pair - 1) + 1) * w + 6 * w + 16))
     achieved = ops / k_m / 1e12
     mhash = kernel_source_hash(("gk_mixed.hip", "gk_pair.h", "gk_internal.h"))
-    mtraffic = traffic_from_profile(mhash, n_pairs, "k_mixed_w10_config3_counters.json")
+    tuning = [report["tile"], report["ppl"], report["sort_e"], report["blocks_per_cu"]]
+    mtraffic = traffic_from_profile(mhash, n_pairs, "k_mixed_w10_config3_counters.json",
+                                    tuning=tuning)
     out = {
         "metric": "filtered pairs/sec, mixed batch (lengths 64-300, per-pair e), 1 MI355X, "
                   "bit-exact",
@@ -382,7 +400,8 @@ def bench_mixed(args, log) -> int:
         "roofline": {"bound": "alu", "kernel": "k_mixed<10>", "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
                      "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": mtraffic,
-                     "ops_per_pair_mean": round(ops / n_pairs, 1), "kernel_source_hash": mhash},
+                     "ops_per_pair_mean": round(ops / n_pairs, 1),
+                     "kernel_ms": round(k_m * 1e3, 4), "kernel_source_hash": mhash},
         "parity": parity,
     }
     print(json.dumps(out), flush=True)
