@@ -47,7 +47,7 @@ def bytes_per_pair(m: int) -> int:
     return m // 4 + m // 4 + 8 + 3 + 2
 
 
-def kernel_source_hash(files=("gk_filter.hip", "gk_pair.h", "gk_internal.h")) -> str:
+def kernel_source_hash(files=("gk_filter.hip", "gk_pair.h", "gk_args.h")) -> str:
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(ROOT, "paper_2103_14978_amd", "csrc", f), "rb") as fh:
@@ -98,6 +98,8 @@ def main() -> int:
                          "65536: one device residency)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-ft", action="store_true",
+                    help="skip the host-to-host filter-time measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 256 MiB device copy kernel first (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -214,6 +216,45 @@ def main() -> int:
                   "accepted_frac": float(np.mean(a_gpu == 1))}
         log(f"parity sample: {mism} mismatches of {len(idx)}")
 
+    # Filter time (Sec. 4.3): host ASCII reads and candidates in pinned host
+    # memory -> gk_filter_host (chunked copies in, device encoding, filter,
+    # copies out, overlapped on three streams) -> results in host memory.
+    # PCIe-inclusive, so it is reported beside the kernel-time headline.
+    ft = None
+    if not args.no_ft:
+        def pinned(a):
+            t = torch.empty(max(a.nbytes, 1), dtype=torch.uint8, pin_memory=True)
+            t.numpy()[:a.nbytes].view(a.dtype)[...] = a
+            return t
+        h_ascii, h_off, h_pos = pinned(ps.reads), pinned(ps.read_off), pinned(ps.cand_pos)
+        h_pr = None if identity else pinned(ps.pair_read)
+        h_acc = torch.empty(n_pairs, dtype=torch.uint8, pin_memory=True)
+        h_est = torch.empty(2 * n_pairs, dtype=torch.uint8, pin_memory=True)
+
+        def ft_step():
+            gk.gk_filter_host(ctx, h_ascii, h_off, h_pos, h_acc, h_est, max_read_len=m,
+                              e_uniform=e, n_reads=ps.n_reads, n_pairs=n_pairs,
+                              pair_read=h_pr)
+        ft_step()
+        ft_steps = max(3, args.steps // 10)
+        t = time.perf_counter()
+        for _ in range(ft_steps):
+            ft_step()
+        ft_wall = (time.perf_counter() - t) / ft_steps
+        a_dev, s_dev = device.results(dp)
+        ft_mism = int(np.sum((h_acc.numpy() != a_dev) |
+                             (h_est.numpy().view(np.uint16) != s_dev)))
+        h2d = ps.reads.nbytes + ps.read_off.nbytes + ps.cand_pos.nbytes
+        ft = {"pairs_per_s": round(n_pairs / ft_wall, 1), "ms_per_step": round(ft_wall * 1e3, 3),
+              "steps": ft_steps, "h2d_bytes": int(h2d), "d2h_bytes": int(3 * n_pairs),
+              "link_GBs": round((h2d + 3 * n_pairs) / ft_wall / 1e9, 2),
+              "mismatches_vs_kernel_path": ft_mism,
+              "what": "host ASCII reads + offsets + positions (pinned) to host results, "
+                      "encoding on the GPU, chunks overlapped on three streams"}
+        log(f"filter time {ft_wall * 1e3:.2f} ms/batch ({n_pairs / ft_wall / 1e6:.1f} M pairs/s), "
+            f"{ft_mism} mismatches vs the kernel path")
+        del h_ascii, h_off, h_pos, h_pr, h_acc, h_est
+
     ops = ops_per_pair(m, e) * n_pairs
     achieved_tops = ops / k_avg_s / 1e12
     khash = kernel_source_hash()
@@ -245,6 +286,13 @@ def main() -> int:
                "sample": f"first {sample} pairs of the same batch, {threads} threads, "
                          f"{dt:.1f}s wall"}
         log(f"cpu baseline {sample / dt:.0f} pairs/s on {threads} threads")
+        one = min(n_pairs, 1 << 16)
+        t = time.perf_counter()
+        oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read[:one], ps.cand_pos[:one], e,
+                            n_threads=1)
+        dt1 = time.perf_counter() - t
+        cpu["one_core"] = {"value": round(one / dt1, 1), "unit": "pairs/s",
+                           "sample": f"first {one} pairs, 1 thread, {dt1:.2f}s wall"}
 
     out = {
         "metric": "filtered pairs/sec (100bp, e=5) on 1 MI355X, bit-exact",
@@ -260,6 +308,7 @@ def main() -> int:
         "kernel_pairs_per_s": round(n_pairs / k_avg_s, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "filter_time": ft,
         "parity": parity,
     }
     print(json.dumps(out), flush=True)
@@ -375,7 +424,7 @@ def bench_mixed(args, log) -> int:
     w = (m_pair + 31) // 32
     ops = int(np.sum(14 * (2 * np.minimum(e_pair, m_pair - 1) + 1) * w + 6 * w + 16))
     achieved = ops / k_m / 1e12
-    mhash = kernel_source_hash(("gk_mixed.hip", "gk_pair.h", "gk_internal.h"))
+    mhash = kernel_source_hash(("gk_mixed.hip", "gk_pair.h", "gk_args.h"))
     tuning = [report["tile"], report["ppl"], report["sort_e"], report["blocks_per_cu"]]
     mtraffic = traffic_from_profile(mhash, n_pairs, "k_mixed_w10_config3_counters.json",
                                     tuning=tuning)

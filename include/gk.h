@@ -91,6 +91,29 @@ const char *gk_last_error(const gk_ctx *ctx);
  */
 int gk_load_reference(gk_ctx *ctx, const char *ascii, uint64_t len);
 
+/*
+ * Reference residency from a 2-bit reference the caller already holds
+ * (Sec. 3.3 fixes 16 bases per 32-bit word; Sec. 3.5 records the unknown
+ * positions beside the codes).
+ *
+ * packed: HOST pointer to ceil(len / 16) words.  Base i is in word i / 16 at
+ * j = i mod 16, with codes A=00 C=01 G=10 T=11 (Sec. 2.1), laid out as
+ * `layout`: GK_READS_SPLIT (low code bit at bit j, high bit at bit 16 + j) or
+ * GK_READS_INTERLEAVED (code at bits 2j, 2j + 1).  Code bits at or beyond len
+ * are ignored.
+ * n_runs: HOST pointer to n_n_runs (start, length) pairs of uint64, or NULL
+ * when n_n_runs is 0: the bases in [start, start + length) are unknown (their
+ * codes are ignored).  Runs may be in any order and may overlap; a run of
+ * length 0 is ignored; a run reaching past len is an error.
+ * Synchronous, like gk_load_reference, and gives the same resident state as
+ * gk_load_reference on the matching ASCII text.  len must be
+ * 1..GK_MAX_REF_LEN (GK_ERANGE above).  Argument errors (GK_EINVAL,
+ * GK_ERANGE) are found before anything changes and keep the previous
+ * reference; a device failure drops it.
+ */
+int gk_load_reference_2bit(gk_ctx *ctx, const uint32_t *packed, uint64_t len, uint32_t layout,
+                           const uint64_t *n_runs, uint64_t n_n_runs);
+
 /* Length and number of unknown bases of the resident reference. */
 int gk_reference_info(const gk_ctx *ctx, uint64_t *len, uint64_t *n_unknown);
 
@@ -163,6 +186,45 @@ typedef struct gk_batch {
  * for n_pairs >= 2^38.
  */
 int gk_filter(gk_ctx *ctx, const gk_batch *batch, void *stream);
+
+/*
+ * Host-to-host filter: the whole path from reads in host memory to results
+ * in host memory (the paper's filter time, Sec. 4.3, as opposed to kernel
+ * time), with the host-to-device copies, the read encoding (Sec. 3.3, on the
+ * GPU), the filter and the device-to-host copies of successive chunks of the
+ * batch overlapped on three streams.
+ *
+ * All pointers are HOST pointers owned by the caller.  Copies overlap with
+ * the kernels only when the buffers are pinned (hipHostMalloc); pageable
+ * memory gives the same results.  Read r is ascii[read_off[r] ..
+ * read_off[r+1]); read_off has n_reads + 1 non-decreasing entries and
+ * read_off[0] == 0.  Pair i compares read pair_read[i] (pair_read NULL: read
+ * i, and then n_pairs == n_reads) with ref[cand_pos[i], cand_pos[i] + m)
+ * under e[i] (or e_uniform when e is NULL); accept[i] and est[i] are as in
+ * gk_filter.  The device buffers are the context's, kept for later calls and
+ * freed with it.
+ * Synchronous: returns once every result is in host memory.  Errors:
+ * GK_EINVAL for NULL buffers, read_off[0] != 0, decreasing offsets (found
+ * while the batch is in flight: the outputs are then unspecified),
+ * n_reads >= 2^30, or max_read_len outside 1..GK_MAX_READ_LEN; GK_ENOREF
+ * without a reference; GK_ENOMEM when the device buffers do not fit.
+ */
+typedef struct gk_host_batch {
+    uint32_t        n_reads;
+    uint32_t        max_read_len;  /* 1..GK_MAX_READ_LEN (longer reads give
+                                      GK_INVALID pairs)                      */
+    const uint8_t  *ascii;         /* HOST reads, ASCII                      */
+    const uint64_t *read_off;      /* HOST, n_reads + 1 entries              */
+    uint64_t        n_pairs;
+    const uint32_t *pair_read;     /* HOST n_pairs, or NULL                  */
+    const uint32_t *cand_pos;      /* HOST n_pairs                           */
+    const uint8_t  *e;             /* HOST n_pairs, or NULL                  */
+    uint32_t        e_uniform;     /* 0..255                                 */
+    uint8_t        *accept;        /* HOST out, n_pairs                      */
+    uint16_t       *est;           /* HOST out, n_pairs                      */
+} gk_host_batch;
+
+int gk_filter_host(gk_ctx *ctx, const gk_host_batch *batch);
 
 /* Tuning options of a context (they never change results). */
 #define GK_OPT_PAIRS_PER_LANE 1   /* plain filter grid: 0 (default) =

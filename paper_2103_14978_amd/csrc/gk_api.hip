@@ -9,6 +9,7 @@
 #include <string>
 
 #include "gk_internal.h"
+#include "gk_reference.h"
 
 namespace {
 
@@ -100,6 +101,7 @@ void gk_destroy(gk_ctx *ctx)
             (void)hipFree(ctx->d_resid);
         if (ctx->capture_stream)
             (void)hipStreamDestroy(ctx->capture_stream);
+        gk_detail_free_host_pipe(ctx);
     }
     delete ctx;
 }
@@ -160,6 +162,91 @@ int gk_load_reference(gk_ctx *ctx, const char *ascii, uint64_t len)
     (void)hipFree(stage);
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference: pack");
+    ctx->ref_len = len;
+    ctx->ref_words = words;
+    ctx->ref_unknown = unknown;
+    ctx->err.clear();
+    return GK_OK;
+}
+
+int gk_load_reference_2bit(gk_ctx *ctx, const uint32_t *packed, uint64_t len, uint32_t layout,
+                           const uint64_t *n_runs, uint64_t n_n_runs)
+{
+    if (!ctx)
+        return GK_EINVAL;
+    if (!packed || len == 0)
+        return fail(ctx, GK_EINVAL, "gk_load_reference_2bit: empty or NULL reference");
+    if (len > GK_MAX_REF_LEN)
+        return fail(ctx, GK_ERANGE, "gk_load_reference_2bit: reference longer than 2^32-1 bases");
+    if (layout != GK_READS_SPLIT && layout != GK_READS_INTERLEAVED)
+        return fail(ctx, GK_EINVAL, "gk_load_reference_2bit: unknown layout");
+    if (n_n_runs > 0 && !n_runs)
+        return fail(ctx, GK_EINVAL, "gk_load_reference_2bit: n_runs is NULL");
+    if (n_n_runs > (1ull << 40))
+        return fail(ctx, GK_EINVAL, "gk_load_reference_2bit: too many runs");
+    for (uint64_t r = 0; r < n_n_runs; ++r) {
+        const uint64_t s = n_runs[2 * r], l = n_runs[2 * r + 1];
+        if (l > 0 && (s >= len || l > len - s))
+            return fail(ctx, GK_EINVAL, "gk_load_reference_2bit: run " + std::to_string(r) +
+                                            " reaches past the reference end");
+    }
+    DeviceGuard g(ctx->device);
+    if (!g.ok)
+        return fail(ctx, GK_EDEVICE, "gk_load_reference_2bit: hipSetDevice failed");
+    free_reference(ctx);
+
+    const uint64_t words = (len + 31) / 32;
+    const uint64_t alloc_words = words + gkd::REF_PAD_WORDS;
+    hipError_t e = hipMalloc(&ctx->ref_planes, alloc_words * sizeof(uint2));
+    if (e != hipSuccess)
+        return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: hipMalloc planes");
+    e = hipMalloc(&ctx->ref_unk, alloc_words * sizeof(uint32_t));
+    if (e != hipSuccess)
+        return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: hipMalloc unknown");
+    e = hipMemset(ctx->ref_planes, 0, alloc_words * sizeof(uint2));
+    if (e == hipSuccess)
+        e = hipMemset(ctx->ref_unk, 0, alloc_words * sizeof(uint32_t));
+    if (e == hipSuccess)
+        e = hipMemset(ctx->d_counter, 0, sizeof(unsigned long long));
+    if (e != hipSuccess)
+        return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: hipMemset");
+
+    // Stage the words in chunks of `step` bases (a multiple of 32, at most
+    // 2^30 bases = 256 MiB of words) and unpack each chunk on the GPU.
+    const uint64_t step = std::min<uint64_t>((len + 31) & ~uint64_t(31), 1ull << 30);
+    uint32_t *stage = nullptr;
+    e = hipMalloc(&stage, step / 16 * sizeof(uint32_t));
+    if (e != hipSuccess)
+        return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: hipMalloc staging");
+    for (uint64_t first = 0; first < len && e == hipSuccess; first += step) {
+        const uint64_t n = std::min<uint64_t>(step, len - first);
+        e = hipMemcpy(stage, packed + first / 16, (n + 15) / 16 * sizeof(uint32_t),
+                      hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = gkd::launch_unpack_reference(stage, first, n, layout, ctx->ref_planes, nullptr);
+        if (e == hipSuccess)
+            e = hipDeviceSynchronize();
+    }
+    (void)hipFree(stage);
+    uint64_t *d_runs = nullptr;
+    if (e == hipSuccess && n_n_runs > 0) {
+        e = hipMalloc(&d_runs, n_n_runs * 2 * sizeof(uint64_t));
+        if (e == hipSuccess)
+            e = hipMemcpy(d_runs, n_runs, n_n_runs * 2 * sizeof(uint64_t), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = gkd::launch_mark_runs(d_runs, n_n_runs, ctx->ref_unk, nullptr);
+    }
+    if (e == hipSuccess && n_n_runs > 0)
+        e = gkd::launch_count_unknown(ctx->ref_unk, words, ctx->d_counter, nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
+    if (d_runs)
+        (void)hipFree(d_runs);
+    unsigned long long unknown = 0;
+    if (e == hipSuccess)
+        e = hipMemcpy(&unknown, ctx->d_counter, sizeof unknown, hipMemcpyDeviceToHost);
+    if (e != hipSuccess)
+        return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: unpack");
     ctx->ref_len = len;
     ctx->ref_words = words;
     ctx->ref_unknown = unknown;

@@ -27,7 +27,7 @@
 // the reference end, are passed as GK_UNDEFINED (Sec. 3.3).
 #pragma once
 
-#include "gk_internal.h"
+#include "gk_args.h"
 
 namespace gkd {
 

@@ -59,6 +59,22 @@ class gk_batch(ctypes.Structure):
     ]
 
 
+class gk_host_batch(ctypes.Structure):
+    _fields_ = [
+        ("n_reads", ctypes.c_uint32),
+        ("max_read_len", ctypes.c_uint32),
+        ("ascii", ctypes.c_void_p),
+        ("read_off", ctypes.c_void_p),
+        ("n_pairs", ctypes.c_uint64),
+        ("pair_read", ctypes.c_void_p),
+        ("cand_pos", ctypes.c_void_p),
+        ("e", ctypes.c_void_p),
+        ("e_uniform", ctypes.c_uint32),
+        ("accept", ctypes.c_void_p),
+        ("est", ctypes.c_void_p),
+    ]
+
+
 class gk_request(ctypes.Structure):
     _fields_ = [
         ("reads", ctypes.c_void_p),
@@ -104,12 +120,16 @@ def lib() -> ctypes.CDLL:
         L.gk_last_error.restype = ctypes.c_char_p
         L.gk_load_reference.argtypes = [vp, ctypes.c_char_p, u64]
         L.gk_load_reference.restype = i32
+        L.gk_load_reference_2bit.argtypes = [vp, vp, u64, u32, vp, u64]
+        L.gk_load_reference_2bit.restype = i32
         L.gk_reference_info.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         L.gk_reference_info.restype = i32
         L.gk_encode_reads.argtypes = [vp, vp, vp, u32, u32, u32, u32, vp, vp, vp, vp]
         L.gk_encode_reads.restype = i32
         L.gk_filter.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
         L.gk_filter.restype = i32
+        L.gk_filter_host.argtypes = [vp, ctypes.POINTER(gk_host_batch)]
+        L.gk_filter_host.restype = i32
         L.gk_filter_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
         L.gk_filter_mixed.restype = i32
         L.gk_tune_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp, u64, ctypes.c_char_p,
@@ -137,7 +157,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
-            "gk_reference_info", "gk_encode_reads", "gk_filter", "gk_set_option",
+            "gk_load_reference_2bit", "gk_reference_info", "gk_encode_reads", "gk_filter", "gk_filter_host", "gk_set_option",
             "gk_get_option", "gk_filter_mixed", "gk_tune_mixed", "gk_server_start",
             "gk_server_submit", "gk_server_wait", "gk_server_counters", "gk_server_stop",
             "gk_clock_us")
@@ -195,6 +215,23 @@ def gk_load_reference(ctx, ascii) -> None:
     _check(ctx, st, "gk_load_reference")
 
 
+def gk_load_reference_2bit(ctx, packed, length: int, layout: int, runs=None) -> None:
+    """packed: host uint32 array of ceil(length / 16) words in `layout`;
+    runs: host array of (start, length) pairs of unknown bases, or None."""
+    import numpy as np
+    p = np.ascontiguousarray(packed, dtype=np.uint32)
+    if p.size < (length + 15) // 16:
+        raise ValueError("gk_load_reference_2bit: packed holds fewer than ceil(length/16) words")
+    if runs is None or len(runs) == 0:
+        r, n_runs = None, 0
+    else:
+        r = np.ascontiguousarray(runs, dtype=np.uint64).reshape(-1, 2)
+        n_runs = r.shape[0]
+    st = lib().gk_load_reference_2bit(ctx, p.ctypes.data, length, layout,
+                                      None if r is None else r.ctypes.data, n_runs)
+    _check(ctx, st, "gk_load_reference_2bit")
+
+
 def gk_reference_info(ctx) -> tuple[int, int]:
     n, u = ctypes.c_uint64(), ctypes.c_uint64()
     _check(ctx, lib().gk_reference_info(ctx, ctypes.byref(n), ctypes.byref(u)),
@@ -244,6 +281,36 @@ def make_batch(*, n_reads, pitch, max_read_len, reads, read_len, pair_read, cand
 
 def gk_filter(ctx, batch: gk_batch, stream=None) -> None:
     _check(ctx, lib().gk_filter(ctx, ctypes.byref(batch), stream_handle(stream)), "gk_filter")
+
+
+def host_ptr(x):
+    """Host address of a numpy array or a CPU torch tensor (pinned or not),
+    or None."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        if x.is_cuda:
+            raise ValueError("host buffer expected, got a device tensor")
+        return x.data_ptr()
+    return x.ctypes.data
+
+
+def gk_filter_host(ctx, ascii, read_off, cand_pos, accept, est, *, max_read_len: int,
+                   pair_read=None, e=None, e_uniform: int = 0, n_reads=None,
+                   n_pairs=None) -> None:
+    """Host buffers in, host results out (synchronous).  Arrays are
+    contiguous numpy arrays of the ABI's dtypes, or CPU torch tensors (e.g.
+    pinned byte buffers) with n_reads and n_pairs given."""
+    if n_reads is None:
+        n_reads = len(read_off) - 1
+    if n_pairs is None:
+        n_pairs = len(cand_pos)
+    b = gk_host_batch(n_reads=n_reads, max_read_len=max_read_len, ascii=host_ptr(ascii),
+                      read_off=host_ptr(read_off), n_pairs=n_pairs,
+                      pair_read=host_ptr(pair_read), cand_pos=host_ptr(cand_pos),
+                      e=host_ptr(e), e_uniform=e_uniform, accept=host_ptr(accept),
+                      est=host_ptr(est))
+    _check(ctx, lib().gk_filter_host(ctx, ctypes.byref(b)), "gk_filter_host")
 
 
 def gk_filter_mixed(ctx, batch: gk_batch, stream=None) -> None:

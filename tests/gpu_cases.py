@@ -97,3 +97,46 @@ def run_gpu_mixed(ctx, reads, read_off, pair_read, cand_pos, e, *, max_read_len,
     finally:
         for k in (options or {}):
             gk.gk_set_option(ctx, k, defaults[k])
+
+
+# ---- host-side 2-bit packing of a reference (for gk_load_reference_2bit) ----
+
+_CODE = np.zeros(256, np.uint32)
+BASE_MASK = np.zeros(256, bool)
+for _ch, _c in zip(b"ACGT", range(4)):
+    _CODE[_ch] = _CODE[_ch + 32] = _c
+    BASE_MASK[_ch] = BASE_MASK[_ch + 32] = True
+
+
+def pack_2bit(ascii, layout, rng, chunk=1 << 24):
+    """16 bases per uint32 word in `layout` (GK_READS_SPLIT: low code bits in
+    bits 0-15, high in 16-31; GK_READS_INTERLEAVED: base j at bits 2j, 2j+1).
+    Unknown bases get random codes, which the loader must ignore."""
+    a = np.asarray(ascii, np.uint8)
+    out = np.zeros((len(a) + 15) // 16, np.uint32)
+    j = np.arange(16, dtype=np.uint32)
+    for first in range(0, len(a), chunk):
+        part = a[first:first + chunk]
+        codes = _CODE[part]
+        unk = ~BASE_MASK[part]
+        if unk.any():
+            codes[unk] = rng.integers(0, 4, int(unk.sum()), dtype=np.uint32)
+        n = (len(part) + 15) // 16 * 16
+        c = np.zeros(n, np.uint32)
+        c[:len(part)] = codes
+        c = c.reshape(-1, 16)
+        if layout == gk.GK_READS_SPLIT:
+            w = ((c & 1) << j).sum(1) | ((c >> 1) << (16 + j)).sum(1)
+        else:
+            w = (c << (2 * j)).sum(1)
+        out[first // 16:first // 16 + len(w)] = w
+    return out
+
+
+def unknown_runs(ascii):
+    """Maximal runs of non-ACGT bytes as (start, length) pairs."""
+    unk = ~BASE_MASK[np.asarray(ascii, np.uint8)]
+    d = np.diff(np.concatenate([[0], unk.astype(np.int8), [0]]))
+    starts = np.nonzero(d == 1)[0]
+    ends = np.nonzero(d == -1)[0]
+    return np.stack([starts, ends - starts], 1).astype(np.uint64)

@@ -115,3 +115,40 @@ def test_config4_full(gkctx):
     for k, (p, o) in enumerate(zip(reqs, objs)):
         ra, rs = run_oracle(ref, p.reads, p.read_off, p.pair_read, p.cand_pos, p.meta["e"])
         assert_same(o.accept, o.est, ra, rs, f"config4 request {k}")
+
+
+def test_config4_2bit_reference(gkctx):
+    """The 3.1 Gbp reference handed over as 2-bit words (several staging
+    chunks, positions above 2^31) plus planted unknown-base runs: 16 requests'
+    pairs through the plain launch, every pair against the oracle."""
+    from gpu_cases import concat_reads, pack_2bit
+    rng = np.random.default_rng(44)
+    ref = gen.c4_reference()
+    L = len(ref)
+    starts = np.sort(rng.choice(L // 4096 - 2, 2000, replace=False)).astype(np.uint64) * 4096
+    starts[-1] = L - 3000
+    lens = rng.integers(1, 2000, len(starts)).astype(np.uint64)
+    for s, l in zip(starts, lens):
+        ref[int(s):int(s + l)] = ord("N")
+    runs = np.stack([starts, lens], 1)
+    reqs = [gen.c4_request(ref, k) for k in range(16)]
+    # Send a quarter of each request's candidates next to a planted run.
+    for p in reqs:
+        k = p.n_pairs // 4
+        near = starts[rng.integers(0, len(starts), k)].astype(np.int64) - rng.integers(0, 300, k)
+        p.cand_pos[:k] = np.clip(near, 0, L - 300).astype(np.uint32)
+    say(f"case: config4 2bit reference, {len(runs)} runs")
+    gk.gk_load_reference_2bit(gkctx, pack_2bit(ref, gk.GK_READS_SPLIT, rng), L,
+                              gk.GK_READS_SPLIT, runs)
+    assert gk.gk_reference_info(gkctx) == (L, int(lens.sum()))
+    for k, p in enumerate(reqs):
+        m = int(p.meta["m"])
+        dr = device.encode_reads(gkctx, p.reads, p.read_off, max_len=m)
+        dp = device.upload_pairs(p.pair_read, p.cand_pos)
+        gk.gk_filter(gkctx, device.batch_for(dr, dp, e_uniform=int(p.meta["e"]), max_read_len=m),
+                     None)
+        torch.cuda.synchronize()
+        a, s = device.results(dp)
+        ra, rs = run_oracle(ref, p.reads, p.read_off, p.pair_read, p.cand_pos, p.meta["e"])
+        assert_same(a, s, ra, rs, f"config4 2bit request {k}")
+        assert np.any(a == gk.GK_UNDEFINED)

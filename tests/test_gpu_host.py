@@ -1,0 +1,139 @@
+"""gk_filter_host: host buffers in, host results out, chunked and overlapped
+on three streams.  Results equal the oracle and the device-buffer path."""
+import numpy as np
+import pytest
+
+import gen
+from gpu_cases import assert_same, concat_reads, run_gpu, run_oracle, say
+
+pytestmark = pytest.mark.gpu
+
+
+def host_filter(ctx, ps, *, max_read_len, e=None, e_uniform=0, identity=False, pinned=False):
+    from paper_2103_14978_amd import gk
+    n = ps.n_pairs
+    if pinned:
+        import torch
+        def pin(a):
+            # pinned bytes, viewed as the array's dtype; the tensor keeps them alive
+            t = torch.empty(max(a.nbytes, 1), dtype=torch.uint8, pin_memory=True)
+            t.numpy()[:a.nbytes].view(a.dtype)[...] = a
+            return t
+        ascii, off, pos = pin(ps.reads), pin(ps.read_off), pin(ps.cand_pos)
+        pr = None if identity else pin(ps.pair_read)
+        ee = None if e is None else pin(e)
+        acc = torch.empty(n, dtype=torch.uint8, pin_memory=True)
+        est = torch.empty(2 * n, dtype=torch.uint8, pin_memory=True)
+        gk.gk_filter_host(ctx, ascii, off, pos, acc, est, max_read_len=max_read_len,
+                          pair_read=pr, e=ee, e_uniform=e_uniform, n_reads=ps.n_reads,
+                          n_pairs=n)
+        return acc.numpy().copy(), est.numpy().view(np.uint16).copy()
+    acc = np.full(n, 0xEE, np.uint8)
+    est = np.full(n, 0xEEEE, np.uint16)
+    gk.gk_filter_host(ctx, ps.reads, ps.read_off, ps.cand_pos, acc, est,
+                      max_read_len=max_read_len, pair_read=None if identity else ps.pair_read,
+                      e=e, e_uniform=e_uniform)
+    return acc, est
+
+
+def test_host_config0(gkctx):
+    from paper_2103_14978_amd import gk
+    ref = gen.c0_reference()
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c0_pairs(ref)
+    assert np.array_equal(ps.pair_read, np.arange(ps.n_pairs))
+    say("case: host config0 identity")
+    a, s = host_filter(gkctx, ps, max_read_len=100, e_uniform=2, identity=True)
+    ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, 2)
+    assert_same(a, s, ra, rs, "host config0")
+
+
+@pytest.mark.parametrize("pinned", [False, True])
+def test_host_multichunk_shuffled(gkctx, pinned):
+    """3M pairs (three chunks) of 150 bp reads with several candidates each,
+    pairs shuffled so that a chunk's pairs need reads of later chunks; per
+    pair e.  Same results as the oracle and as gk_filter on device buffers."""
+    from paper_2103_14978_amd import gk
+    ref = gen.c1_reference()
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c2_pairs(ref, 150, 7, n_pairs=3 << 20)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(ps.n_pairs)
+    ps.pair_read = ps.pair_read[perm].copy()
+    ps.cand_pos = ps.cand_pos[perm].copy()
+    e = rng.integers(0, 16, ps.n_pairs).astype(np.uint8)
+    say(f"case: host multichunk pinned={pinned} pairs={ps.n_pairs}")
+    a, s = host_filter(gkctx, ps, max_read_len=150, e=e, pinned=pinned)
+    a2, s2, _ = run_gpu(gkctx, ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, e,
+                        max_read_len=150, load_ref=False)
+    assert_same(a, s, a2, s2, "host vs device buffers")
+    idx = np.sort(rng.choice(ps.n_pairs, 1 << 16, replace=False))
+    ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read[idx], ps.cand_pos[idx], e[idx])
+    assert_same(a[idx], s[idx], ra, rs, "host vs oracle")
+
+
+def test_host_identity_multichunk(gkctx):
+    """2^21 + 333 pairs, one per read (the ragged last chunk), e uniform."""
+    from paper_2103_14978_amd import gk
+    ref = gen.c1_reference()
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c1_pairs(ref, 5, n_pairs=(1 << 21) + 333)
+    say("case: host identity multichunk")
+    a, s = host_filter(gkctx, ps, max_read_len=100, e_uniform=5, identity=True, pinned=True)
+    a2, s2, _ = run_gpu(gkctx, ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, 5,
+                        max_read_len=100, load_ref=False, identity_as_null=True)
+    assert_same(a, s, a2, s2, "host identity vs device buffers")
+    idx = np.arange(0, ps.n_pairs, 97)
+    ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read[idx], ps.cand_pos[idx], 5)
+    assert_same(a[idx], s[idx], ra, rs, "host identity vs oracle")
+
+
+def test_host_status_and_errors(gkctx):
+    """Unknown bases, over-long reads and bad read indices give per-pair
+    codes; bad offsets and buffers are call errors; no reference is ENOREF."""
+    from paper_2103_14978_amd import gk
+    rng = np.random.default_rng(9)
+    ref = rng.choice(np.frombuffer(b"ACGT", np.uint8), 20000).copy()
+    gk.gk_load_reference(gkctx, ref)
+    seqs = [ref[100:200].tobytes(), b"ACGTN" * 20, ref[300:460].tobytes(), b""]
+    reads, off = concat_reads(seqs)
+    pr = np.array([0, 1, 2, 3, 7, 0], np.uint32)
+    pos = np.array([100, 0, 300, 0, 0, 19950], np.uint32)
+    ps = gen.PairSet(reads, off, np.diff(off).astype(np.uint16), pr, pos,
+                     np.zeros(len(pr), np.uint8), np.zeros(len(pr), np.uint8), {})
+    a, s = host_filter(gkctx, ps, max_read_len=128, e_uniform=3)
+    assert list(a) == [gk.GK_ACCEPT, gk.GK_UNDEFINED, gk.GK_INVALID, gk.GK_INVALID,
+                       gk.GK_INVALID, gk.GK_UNDEFINED]
+    assert s[0] == 0 and all(v == gk.GK_EST_NONE for v in s[1:])
+
+    acc = np.zeros(len(pr), np.uint8)
+    est = np.zeros(len(pr), np.uint16)
+    bad_first = off.copy()
+    bad_first[0] = 1
+    bad_mid = off.copy()
+    bad_mid[2] = bad_mid[1] - 1
+    bad_end = off.copy()
+    bad_end[1] = off[-1] + 5
+    for o in (bad_first, bad_mid):
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_filter_host(gkctx, reads, o, pos, acc, est, max_read_len=128, pair_read=pr)
+        assert ei.value.status == gk.GK_EINVAL
+    with pytest.raises(gk.GkError) as ei:
+        gk.gk_filter_host(gkctx, reads, bad_end, pos, acc, est, max_read_len=128, pair_read=pr)
+    assert ei.value.status == gk.GK_EINVAL
+    with pytest.raises(gk.GkError) as ei:   # NULL pair_read needs one pair per read
+        gk.gk_filter_host(gkctx, reads, off, pos, acc, est, max_read_len=128)
+    assert ei.value.status == gk.GK_EINVAL
+    with pytest.raises(gk.GkError) as ei:
+        gk.gk_filter_host(gkctx, reads, off, pos, acc, est, max_read_len=600, pair_read=pr)
+    assert ei.value.status == gk.GK_EINVAL
+    ctx2 = gk.gk_create(0)
+    try:
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_filter_host(ctx2, reads, off, pos, acc, est, max_read_len=128, pair_read=pr)
+        assert ei.value.status == gk.GK_ENOREF
+    finally:
+        gk.gk_destroy(ctx2)
+    # The context still works after the errors.
+    a, s = host_filter(gkctx, ps, max_read_len=128, e_uniform=3)
+    assert a[0] == gk.GK_ACCEPT
