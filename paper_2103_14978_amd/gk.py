@@ -342,7 +342,10 @@ class Request:
     """A gk_request over host numpy arrays, which it keeps alive, with its own
     output arrays (accept uint8, est uint16)."""
 
-    def __init__(self, reads, read_off, cand_pos, e: int, pair_read=None, t_arrival_us: int = 0):
+    def __init__(self, reads, read_off, cand_pos, e: int, pair_read=None, t_arrival_us: int = 0,
+                 accept=None, est=None):
+        """accept / est: output arrays to fill (e.g. views of pinned memory);
+        allocated here when None."""
         import numpy as np
         self.reads = np.ascontiguousarray(reads, dtype=np.uint8)
         self.read_off = np.ascontiguousarray(read_off, dtype=np.uint64)
@@ -350,8 +353,12 @@ class Request:
         self.pair_read = (np.ascontiguousarray(pair_read, dtype=np.uint32)
                           if pair_read is not None else None)
         n = len(self.cand_pos)
-        self.accept = np.zeros(n, dtype=np.uint8)
-        self.est = np.zeros(n, dtype=np.uint16)
+        self.accept = np.zeros(n, dtype=np.uint8) if accept is None else accept
+        self.est = np.zeros(n, dtype=np.uint16) if est is None else est
+        if (self.accept.dtype != np.uint8 or self.est.dtype != np.uint16 or
+                len(self.accept) != n or len(self.est) != n or
+                not self.accept.flags.c_contiguous or not self.est.flags.c_contiguous):
+            raise ValueError("Request: accept must be uint8[n_pairs], est uint16[n_pairs]")
         r = gk_request()
         r.reads = self.reads.ctypes.data if self.reads.size else None
         r.read_off = self.read_off.ctypes.data

@@ -35,7 +35,8 @@ def ref100m():
 
 def test_config1_full(gkctx, ref100m):
     """2^24 pairs of 100 bp, e = 5, one candidate per read (pair_read NULL),
-    split layout, automatic grid: the benchmark's launch."""
+    split layout, automatic grid: the benchmark's launch, every pair against
+    the oracle."""
     ref = ref100m
     gk.gk_load_reference(gkctx, ref)
     ps = gen.c1_pairs(ref, 5)
@@ -46,7 +47,8 @@ def test_config1_full(gkctx, ref100m):
     torch.cuda.synchronize()
     a, s = device.results(dp)
     check_properties(a, s, 5, 100, "config1")
-    sample_check(ref, ps, a, s, 5, 1 << 15, 1, "config1 sample")
+    ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, 5)
+    assert_same(a, s, ra, rs, "config1 every pair")
 
 
 @pytest.mark.parametrize("m,es", [(150, (3, 7, 15)), (250, (5, 12, 25))])
