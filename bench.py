@@ -98,6 +98,8 @@ def main() -> int:
                          "65536: one device residency)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-parity", action="store_true")
+    ap.add_argument("--no-verify", action="store_true",
+                    help="skip the verification (edit distance) measurement")
     ap.add_argument("--no-ft", action="store_true",
                     help="skip the host-to-host filter-time measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -109,7 +111,8 @@ def main() -> int:
                          "lengths and per-pair e, persistent launch vs one launch per "
                          "(length, e) group; served: Poisson request stream over a 3.1 Gbp "
                          "reference, batched server vs sequential per-request launches")
-    ap.add_argument("--lambdas", default="50,100,200,500,1000,2000,3000,4000,6000,8000",
+    ap.add_argument("--lambdas",
+                    default="50,100,200,500,1000,2000,3000,3500,4000,4500,5000,6000,8000",
                     help="served: arrival rates (requests/s)")
     ap.add_argument("--duration", type=float, default=6.0,
                     help="served: seconds of arrivals per rate and mode")
@@ -219,6 +222,57 @@ def main() -> int:
                   "accepted_frac": float(np.mean(a_gpu == 1))}
         log(f"parity sample: {mism} mismatches of {len(idx)}")
 
+    # Verification of the accepted pairs (the step the filter exists to cut,
+    # Sec. 3.5, Sec. 5.3): gk_verify after gk_filter, against gk_verify of
+    # every pair with no filter.
+    verify = None
+    if not args.no_verify:
+        dist = torch.empty(n_pairs, dtype=torch.int16, device=dev)
+
+        def timed_ms(fn, k):
+            for _ in range(2):
+                fn()
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(k)]
+            for a0, a1 in ev:
+                a0.record(stream)
+                fn()
+                a1.record(stream)
+            torch.cuda.synchronize()
+            return float(np.mean([a0.elapsed_time(a1) for a0, a1 in ev]))
+        vk = max(3, args.steps // 10)
+        ms_after = timed_ms(lambda: gk.gk_verify(ctx, batch, dp.accept, dist, stream), vk)
+        ms_fv = timed_ms(lambda: (gk.gk_filter(ctx, batch, stream),
+                                  gk.gk_verify(ctx, batch, dp.accept, dist, stream)), vk)
+        ms_all = timed_ms(lambda: gk.gk_verify(ctx, batch, None, dist, stream), vk)
+        a_gpu, _ = device.results(dp)
+        accepted = int(np.sum(a_gpu == gk.GK_ACCEPT))
+        gk.gk_verify(ctx, batch, dp.accept, dist, stream)
+        torch.cuda.synchronize()
+        d_gpu = dist.cpu().numpy().view(np.uint16)
+        vmism = None
+        if not args.no_parity:
+            import oracle
+            acc_idx = np.nonzero(a_gpu == gk.GK_ACCEPT)[0]
+            rng = np.random.default_rng(777)
+            idx = np.sort(rng.choice(acc_idx, size=min(len(acc_idx), 1 << 14), replace=False))
+            want = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[idx],
+                                            ps.cand_pos[idx], e, n_threads=gen.default_threads())
+            vmism = int(np.sum(d_gpu[idx] != want))
+        within = int(np.sum(d_gpu <= e))
+        verify = {"accepted_pairs": accepted, "reduction": round(1 - accepted / n_pairs, 4),
+                  "verified_within_e": within,
+                  "verify_ms": round(ms_after, 4), "filter_plus_verify_ms": round(ms_fv, 4),
+                  "verify_all_ms": round(ms_all, 4),
+                  "filter_plus_verify_pairs_per_s": round(n_pairs / (ms_fv / 1e3), 1),
+                  "speedup_vs_verify_all": round(ms_all / ms_fv, 3),
+                  "sampled_mismatches": vmism,
+                  "what": "banded bit-parallel edit distance (cap e+1) of the GK_ACCEPT pairs"}
+        log(f"verify {ms_after:.3f} ms for {accepted} accepted pairs; filter+verify "
+            f"{ms_fv:.3f} ms vs verify-all {ms_all:.3f} ms")
+        del dist
+
     # Filter time (Sec. 4.3): host ASCII reads and candidates in pinned host
     # memory -> gk_filter_host (chunked copies in, device encoding, filter,
     # copies out, overlapped on three streams) -> results in host memory.
@@ -320,6 +374,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "filter_time": ft,
+        "verification": verify,
         "parity": parity,
     }
     print(json.dumps(out), flush=True)
@@ -537,6 +592,7 @@ def bench_served(args, log) -> int:
             reqs = []
             done = []
             outs = {}
+            lag = []          # submitter lateness: actual submit - scheduled arrival
             t0 = gk.gk_clock_us() + 200_000
             arrivals = t0 + (np.cumsum(gaps) * 1e6).astype(np.int64)
 
@@ -558,6 +614,7 @@ def bench_served(args, log) -> int:
                                    pair_read=ps.pair_read, t_arrival_us=int(arrivals[k]),
                                    accept=acc, est=est)
                     reqs.append(r)
+                    lag.append(gk.gk_clock_us() - int(arrivals[k]))
                     tickets.append(gk.gk_server_submit(srv, r))
 
             th = threading.Thread(target=submit)
@@ -598,7 +655,9 @@ def bench_served(args, log) -> int:
                    "p50_ms": pct(50), "p99_ms": pct(99), "p999_ms": pct(99.9),
                    "max_ms": round(float(lat.max()), 3) if len(lat) else None,
                    "pairs_per_s": round(float(sum(n for _, n in done)) / span, 1),
-                   "ticks": ticks, "max_requests_per_tick": per_tick}
+                   "ticks": ticks, "max_requests_per_tick": per_tick,
+                   "submit_lag_p99_ms": round(float(np.percentile(lag, 99)) / 1e3, 3)
+                   if lag else None}
             results[mode_name].append(rec)
             log(f"{mode_name} lambda={lam}: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms, "
                 f"{rec['pairs_per_s'] / 1e6:.1f} M pairs/s, unfinished {unfinished}")

@@ -226,6 +226,30 @@ typedef struct gk_host_batch {
 
 int gk_filter_host(gk_ctx *ctx, const gk_host_batch *batch);
 
+/*
+ * Verification of filtered pairs: the exact edit distance that a read
+ * mapper's verification step computes for the pairs the filter passes
+ * (Sec. 3.3, Sec. 3.5): unit-cost global alignment of the read with its
+ * window ref[cand_pos[i], cand_pos[i] + m), the ground truth of Sec. 4.4.
+ *
+ * batch: as for gk_filter (its accept, est and accept_bits are not used).
+ * accept: DEVICE, n_pairs codes written by gk_filter / gk_filter_mixed, or
+ * NULL to verify every pair.
+ * dist: DEVICE out, n_pairs: min(edit distance, e_i + 1) for each pair with
+ * accept[i] == GK_ACCEPT (every pair when accept is NULL), so dist <= e_i
+ * exactly when the pair lies within e_i edits; GK_EST_NONE for pairs not
+ * verified, for pairs gk_filter marks GK_UNDEFINED or GK_INVALID, and for
+ * e_i > GK_VERIFY_MAX_E.
+ * Asynchronous on stream.  Uses context-owned scratch (a pair list of up to
+ * 2^30 entries, allocated on first use): calls on one context must not
+ * overlap on different streams.  Errors as gk_filter, plus GK_EINVAL for a
+ * NULL dist.
+ */
+#define GK_VERIFY_MAX_E 31u
+
+int gk_verify(gk_ctx *ctx, const gk_batch *batch, const uint8_t *accept, uint16_t *dist,
+              void *stream);
+
 /* Tuning options of a context (they never change results). */
 #define GK_OPT_PAIRS_PER_LANE 1   /* plain filter grid: 0 (default) =
                                      automatic from e and the read length;

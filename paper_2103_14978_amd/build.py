@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgk.so")
 SOURCES = ["gk_api.hip", "gk_encode.hip", "gk_filter.hip", "gk_host.hip", "gk_mixed.hip",
-           "gk_reference.hip", "gk_server.hip"]
+           "gk_reference.hip", "gk_server.hip", "gk_verify.hip"]
 ARCH = os.environ.get("GK_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

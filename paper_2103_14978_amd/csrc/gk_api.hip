@@ -10,6 +10,7 @@
 
 #include "gk_internal.h"
 #include "gk_reference.h"
+#include "gk_verify.h"
 
 namespace {
 
@@ -102,6 +103,10 @@ void gk_destroy(gk_ctx *ctx)
         if (ctx->capture_stream)
             (void)hipStreamDestroy(ctx->capture_stream);
         gk_detail_free_host_pipe(ctx);
+        if (ctx->d_verify_list)
+            (void)hipFree(ctx->d_verify_list);
+        if (ctx->d_verify_count)
+            (void)hipFree(ctx->d_verify_count);
     }
     delete ctx;
 }
@@ -431,6 +436,46 @@ int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
                                       (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "gk_filter: launch");
+    return GK_OK;
+}
+
+int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *dist,
+              void *stream)
+{
+    if (!ctx)
+        return GK_EINVAL;
+    gkd::FilterArgs a{};
+    const int st = prepare_batch(ctx, b, "gk_verify", a);
+    if (st == 1)
+        return GK_OK;
+    if (st != GK_OK)
+        return st;
+    if (!dist)
+        return fail(ctx, GK_EINVAL, "gk_verify: dist is NULL");
+    DeviceGuard g(ctx->device);
+    if (!g.ok)
+        return fail(ctx, GK_EDEVICE, "gk_verify: hipSetDevice failed");
+    const uint64_t need = std::min<uint64_t>(b->n_pairs, 1ull << 30);
+    if (need > ctx->verify_cap) {
+        if (ctx->d_verify_list)
+            (void)hipFree(ctx->d_verify_list);
+        ctx->d_verify_list = nullptr;
+        ctx->verify_cap = 0;
+        hipError_t e = hipMalloc(&ctx->d_verify_list, need * sizeof(uint32_t));
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_verify: hipMalloc list");
+        ctx->verify_cap = need;
+    }
+    if (!ctx->d_verify_count) {
+        hipError_t e = hipMalloc(&ctx->d_verify_count, sizeof(uint32_t));
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_verify: hipMalloc count");
+    }
+    const uint32_t words = (b->max_read_len + 31) / 32;
+    hipError_t e = gkd::launch_verify(a, accept, dist, ctx->d_verify_list, ctx->d_verify_count,
+                                      words, b->read_layout, ctx->cu_count, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "gk_verify: launch");
     return GK_OK;
 }
 

@@ -316,22 +316,23 @@ __device__ __forceinline__ void load_data(const FilterArgs &a, const PairIdx &p,
         d.win[w] = 32u * w < span ? src[w] : make_uint2(0u, 0u);
 }
 
-// Filter one pair whose loads have arrived: returns the result code and sets
-// est (GK_EST_NONE unless REJECT / ACCEPT).  With GENERAL false the caller
-// guarantees 32(W-1) < m <= 32W and min(e, m-1) <= 31 for every valid pair,
-// and only the register-light fast path is compiled.
-template <int W, int L, bool GENERAL = true>
-__device__ __forceinline__ uint32_t compute_pair(const FilterArgs &a, const PairIdx &p,
-                                                 const PairData<W> &d, uint32_t &est)
+// Whether a pair whose loads have arrived can be compared (Sec. 3.3): returns
+// PAIR_OK and sets m, or GK_INVALID (read length 0 or above max_read_len, or
+// no such read) or GK_UNDEFINED (an unknown base in the read or the window, or
+// a window past the reference end).
+constexpr uint32_t PAIR_OK = 0xFFu;
+
+template <int W>
+__device__ __forceinline__ uint32_t pair_gate(const FilterArgs &a, const PairIdx &p,
+                                              const PairData<W> &d, uint32_t &m)
 {
-    est = GK_EST_NONE;
-    const uint32_t m = p.r < a.n_reads ? d.m : 0u;
+    m = p.r < a.n_reads ? d.m : 0u;
     if (m == 0u || m > a.max_read_len)
         return GK_INVALID;
     if ((uint64_t)p.pos + m > a.ref_len || (a.read_has_n && a.read_has_n[p.r]))
         return GK_UNDEFINED;
-    const uint32_t s = p.pos & 31u;
     if (a.ref_has_unknown) {
+        const uint32_t s = p.pos & 31u;
         const uint32_t *u = a.ref_unk + (p.pos >> 5);
         uint32_t any = 0, cu = u[0];
 #pragma unroll
@@ -343,9 +344,17 @@ __device__ __forceinline__ uint32_t compute_pair(const FilterArgs &a, const Pair
         if (any)
             return GK_UNDEFINED;
     }
-    // Window planes: funnel-shift the gathered words by pos mod 32, clear
-    // bits at or beyond m.
-    uint32_t gh[W], gl[W], rh[W], rl[W];
+    return PAIR_OK;
+}
+
+// Read and window bit-planes of a pair that passed pair_gate: the window
+// words are funnel-shifted by pos mod 32 and cleared at or beyond m.
+template <int W, int L>
+__device__ __forceinline__ void pair_planes(const PairIdx &p, const PairData<W> &d, uint32_t m,
+                                            uint32_t (&gh)[W], uint32_t (&gl)[W],
+                                            uint32_t (&rh)[W], uint32_t (&rl)[W])
+{
+    const uint32_t s = p.pos & 31u;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         const uint32_t v = ones_below((int)m - 32 * w);
@@ -353,6 +362,23 @@ __device__ __forceinline__ uint32_t compute_pair(const FilterArgs &a, const Pair
         gl[w] = funnel(d.win[w + 1].y, d.win[w].y, s) & v;
         planes_from_words<L>(d.words[2 * w], d.words[2 * w + 1], rh[w], rl[w]);
     }
+}
+
+// Filter one pair whose loads have arrived: returns the result code and sets
+// est (GK_EST_NONE unless REJECT / ACCEPT).  With GENERAL false the caller
+// guarantees 32(W-1) < m <= 32W and min(e, m-1) <= 31 for every valid pair,
+// and only the register-light fast path is compiled.
+template <int W, int L, bool GENERAL = true>
+__device__ __forceinline__ uint32_t compute_pair(const FilterArgs &a, const PairIdx &p,
+                                                 const PairData<W> &d, uint32_t &est)
+{
+    est = GK_EST_NONE;
+    uint32_t m;
+    const uint32_t gate = pair_gate<W>(a, p, d, m);
+    if (gate != PAIR_OK)
+        return gate;
+    uint32_t gh[W], gl[W], rh[W], rl[W];
+    pair_planes<W, L>(p, d, m, gh, gl, rh, rl);
     const uint32_t kmax = p.e < m - 1u ? p.e : m - 1u;
     if (!GENERAL || (m > 32u * (W - 1) && kmax <= 31u)) {
         const uint32_t vtop = ones_below((int)m - 32 * (W - 1));

@@ -21,6 +21,7 @@ GK_ECANCELED = -8
 GK_SERVER_BATCHED, GK_SERVER_SEQUENTIAL = 0, 1
 GK_REJECT, GK_ACCEPT, GK_UNDEFINED, GK_INVALID = 0, 1, 2, 3
 GK_EST_NONE = 0xFFFF
+GK_VERIFY_MAX_E = 31
 GK_MAX_READ_LEN = 512
 GK_READS_SPLIT, GK_READS_INTERLEAVED = 0, 1
 GK_OPT_PAIRS_PER_LANE = 1
@@ -130,6 +131,8 @@ def lib() -> ctypes.CDLL:
         L.gk_filter.restype = i32
         L.gk_filter_host.argtypes = [vp, ctypes.POINTER(gk_host_batch)]
         L.gk_filter_host.restype = i32
+        L.gk_verify.argtypes = [vp, ctypes.POINTER(gk_batch), vp, vp, vp]
+        L.gk_verify.restype = i32
         L.gk_filter_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
         L.gk_filter_mixed.restype = i32
         L.gk_tune_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp, u64, ctypes.c_char_p,
@@ -157,7 +160,7 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
-            "gk_load_reference_2bit", "gk_reference_info", "gk_encode_reads", "gk_filter", "gk_filter_host", "gk_set_option",
+            "gk_load_reference_2bit", "gk_reference_info", "gk_encode_reads", "gk_filter", "gk_filter_host", "gk_verify", "gk_set_option",
             "gk_get_option", "gk_filter_mixed", "gk_tune_mixed", "gk_server_start",
             "gk_server_submit", "gk_server_wait", "gk_server_counters", "gk_server_stop",
             "gk_clock_us")
@@ -311,6 +314,13 @@ def gk_filter_host(ctx, ascii, read_off, cand_pos, accept, est, *, max_read_len:
                       e=host_ptr(e), e_uniform=e_uniform, accept=host_ptr(accept),
                       est=host_ptr(est))
     _check(ctx, lib().gk_filter_host(ctx, ctypes.byref(b)), "gk_filter_host")
+
+
+def gk_verify(ctx, batch: gk_batch, accept, dist, stream=None) -> None:
+    """dist (device uint16, n_pairs) = min(edit distance, e + 1) for pairs
+    whose device accept code is GK_ACCEPT (every pair when accept is None)."""
+    _check(ctx, lib().gk_verify(ctx, ctypes.byref(batch), ptr(accept), ptr(dist),
+                                stream_handle(stream)), "gk_verify")
 
 
 def gk_filter_mixed(ctx, batch: gk_batch, stream=None) -> None:

@@ -6,7 +6,7 @@ oracle filters every pair (with the GPU version's leading/trailing
 refinement of Sec. 3.4, and without it, which is the GateKeeper-FPGA
 behaviour) and the banded Levenshtein distance (unit-cost global alignment
 of the read and its window, capped at e + 1) decides which pairs truly lie
-within e edits.  As in Sec. 4.2:
+within e edits.  As in Sec. 4.4 and Sec. 5.1:
     FA = accepted although lev > e,   FA rate = FA / #(lev > e)
     FR = rejected although lev <= e,  FR rate = FR / #(lev <= e)
 Pairs with unknown bases or windows past the reference end are passed

@@ -1,5 +1,5 @@
 """Accuracy of the filter against edit distance on config 0 (all 10,000
-pairs), as the FA/FR definitions of Sec. 4.2 count it: the directions the
+pairs), as the FA/FR definitions of Sec. 4.4 count it: the directions the
 method fixes must hold."""
 import numpy as np
 import pytest

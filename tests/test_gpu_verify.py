@@ -1,0 +1,127 @@
+"""gk_verify: the edit distance of the verification step the filter precedes,
+capped at e + 1, against the oracle's banded dynamic programme."""
+import numpy as np
+import pytest
+import torch
+
+import gen
+import oracle
+from gpu_cases import concat_reads, say
+from paper_2103_14978_amd import device, gk
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_dist(ref, reads, off, pair_read, cand_pos, e):
+    """min(lev, e + 1) per pair, grouped by threshold."""
+    e = np.asarray(e)
+    out = np.zeros(len(cand_pos), np.uint16)
+    for v in np.unique(e):
+        idx = np.nonzero(e == v)[0]
+        out[idx] = oracle.levenshtein_batch(reads, off, ref, pair_read[idx], cand_pos[idx],
+                                            int(v), n_threads=gen.default_threads())
+    return out
+
+
+def edited_pairs(rng, ref, n, max_len=300, max_e=31, min_len=1):
+    """Reads copied from the reference with random substitutions and 1-3 base
+    insertions / deletions, paired with their origin or a nearby shift."""
+    seqs, pos = [], []
+    L = len(ref)
+    for _ in range(n):
+        m = int(rng.integers(min_len, max_len + 1))
+        p = int(rng.integers(0, L - m - 8))
+        src = list(ref[p:p + m + 8].tobytes())
+        for _ in range(int(rng.poisson(1 + m / 25))):
+            q = int(rng.integers(0, len(src)))
+            k = rng.random()
+            if k < 0.6:
+                src[q] = int(rng.choice(np.frombuffer(b"ACGT", np.uint8)))
+            elif k < 0.8:
+                for _ in range(int(rng.integers(1, 4))):
+                    src.insert(q, int(rng.choice(np.frombuffer(b"ACGT", np.uint8))))
+            elif len(src) > m + 3:
+                del src[q:q + int(rng.integers(1, 4))]
+        seqs.append(bytes(src[:m]))
+        pos.append(min(max(p + int(rng.integers(-2, 3)), 0), L - m))
+    reads, off = concat_reads(seqs)
+    e = rng.integers(0, max_e + 1, n).astype(np.uint8)
+    return reads, off, np.arange(n, dtype=np.uint32), np.array(pos, np.uint32), e
+
+
+def verify(ctx, reads, off, pr, pos, e, max_len, accept=None):
+    dr = device.encode_reads(ctx, reads, off, max_len=max_len)
+    dp = device.upload_pairs(pr, pos, e)
+    b = device.batch_for(dr, dp, max_read_len=max_len)
+    dist = torch.empty(len(pos), dtype=torch.int16, device="cuda")
+    acc = None if accept is None else torch.from_numpy(accept).cuda()
+    gk.gk_verify(ctx, b, acc, dist, None)
+    torch.cuda.synchronize()
+    return dist.cpu().numpy().view(np.uint16)
+
+
+@pytest.mark.parametrize("max_len", [64, 150, 300])
+def test_verify_all_pairs(gkctx, max_len):
+    rng = np.random.default_rng(max_len)
+    ref = gen.c0_reference()
+    gk.gk_load_reference(gkctx, ref)
+    reads, off, pr, pos, e = edited_pairs(rng, ref, 6000, max_len=max_len)
+    say(f"case: verify all, max_len={max_len}")
+    d = verify(gkctx, reads, off, pr, pos, e, max_len)
+    want = oracle_dist(ref, reads, off, pr, pos, e)
+    bad = np.nonzero(d != want)[0]
+    assert len(bad) == 0, (f"{len(bad)} differ; first {bad[0]}: gpu {d[bad[0]]} oracle "
+                           f"{want[bad[0]]} e={e[bad[0]]} m={off[bad[0] + 1] - off[bad[0]]}")
+    assert np.any(d <= e) and np.any(d == e.astype(np.uint16) + 1)
+
+
+def test_verify_thresholds_and_lengths(gkctx):
+    """Every e in 0..31 (the 32-bit band up to 15, the 64-bit band above) on
+    lengths 1..40 and 500-512, and e > 31 gives GK_EST_NONE."""
+    rng = np.random.default_rng(77)
+    ref = gen.c0_reference()
+    gk.gk_load_reference(gkctx, ref)
+    reads, off, pr, pos, _ = edited_pairs(rng, ref, 4000, max_len=40)
+    e = (np.arange(len(pos)) % 33).astype(np.uint8)
+    say("case: verify thresholds 0..32, lengths 1..40")
+    d = verify(gkctx, reads, off, pr, pos, e, 40)
+    ok = e <= 31
+    want = oracle_dist(ref, reads, off, pr[ok], pos[ok], e[ok])
+    assert np.array_equal(d[ok], want)
+    assert np.all(d[~ok] == gk.GK_EST_NONE)
+    reads, off, pr, pos, e = edited_pairs(rng, ref, 300, max_len=512, min_len=500)
+    say("case: verify lengths 500-512")
+    d = verify(gkctx, reads, off, pr, pos, e, 512)
+    want = oracle_dist(ref, reads, off, pr, pos, e)
+    assert np.array_equal(d, want)
+
+
+def test_verify_after_filter_and_status(gkctx):
+    """Only GK_ACCEPT pairs are verified; rejected, undefined (unknown base,
+    window past the end) and invalid pairs give GK_EST_NONE."""
+    ref = gen.c1_reference(2_000_000)
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c1_pairs(ref, 5, n_pairs=1 << 16)
+    say("case: verify after filter, config 1 slice")
+    dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=100)
+    dp = device.upload_pairs(None, ps.cand_pos)
+    b = device.batch_for(dr, dp, e_uniform=5, max_read_len=100)
+    gk.gk_filter(gkctx, b, None)
+    dist = torch.empty(ps.n_pairs, dtype=torch.int16, device="cuda")
+    gk.gk_verify(gkctx, b, dp.accept, dist, None)
+    torch.cuda.synchronize()
+    a, _ = device.results(dp)
+    d = dist.cpu().numpy().view(np.uint16)
+    acc = a == gk.GK_ACCEPT
+    assert np.all(d[~acc] == gk.GK_EST_NONE)
+    want = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[acc],
+                                    ps.cand_pos[acc], 5, n_threads=gen.default_threads())
+    assert np.array_equal(d[acc], want)
+    # status cases through the all-pairs form
+    seqs = [ref[10:110].tobytes(), b"ACGTN" * 20, b"", ref[500:600].tobytes()]
+    reads, off = concat_reads(seqs)
+    pr = np.array([0, 1, 2, 3, 9], np.uint32)
+    pos = np.array([10, 0, 0, len(ref) - 50, 0], np.uint32)
+    e = np.array([3, 3, 3, 3, 3], np.uint8)
+    d = verify(gkctx, reads, off, pr, pos, e, 128)
+    assert list(d) == [0] + [gk.GK_EST_NONE] * 4
