@@ -24,6 +24,7 @@ REJECT, ACCEPT, UNDEFINED, INVALID = 0, 1, 2, 3
 EST_NONE = 0xFFFF
 MAX_LEN = 512
 NO_REFINE = 1
+HAMMING_FASTPATH = 2
 STAGE_RAW, STAGE_AMENDED, STAGE_REFINED = 0, 1, 2
 
 

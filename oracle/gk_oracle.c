@@ -116,6 +116,17 @@ uint32_t gko_filter_pair_trace(const char *read, uint32_t m, const char *ref,
             return GKO_UNDEFINED;
     }
 
+    /* Optional fast path: accept on the Hamming distance alone. */
+    if (flags & GKO_HAMMING_FASTPATH) {
+        uint32_t hd = 0;
+        for (i = 0; i < m; i++)
+            hd += (rc[i] != gc[i]);
+        if (hd <= e) {
+            *est = (uint16_t)hd;
+            return GKO_ACCEPT;
+        }
+    }
+
     /* Masks with a shift of m or more bases are all 1s once refined, so
        they never change the AND; stopping at min(e, m) is exact. */
     uint32_t e_eff = e < m ? e : m;

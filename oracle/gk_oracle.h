@@ -29,6 +29,10 @@ extern "C" {
 /* Flags. */
 #define GKO_NO_REFINE 1u   /* skip the leading/trailing refinement (Sec. 3.4):
                               the original GateKeeper behaviour               */
+#define GKO_HAMMING_FASTPATH 2u /* a variant the paper does not describe: a
+                              pair whose Hamming distance (count of differing
+                              codes) is at most e is accepted with that count
+                              as its estimate; otherwise the masks decide     */
 
 /* Stages recorded by gko_filter_pair_trace, per mask. */
 #define GKO_STAGE_RAW     0
@@ -52,7 +56,8 @@ uint32_t gko_filter_pair(const char *read, uint32_t m, const char *ref,
    (2*e_eff + 1) * 3 * m bytes where e_eff = min(e, m); mask slot s is
    d = 0 for s = 0, d = +k (deletion) for s = 2k-1, d = -k (insertion) for
    s = 2k; each slot holds stages RAW, AMENDED, REFINED of m bytes each.
-   Slots are written only when the result is REJECT or ACCEPT. */
+   Slots are written only when the result is REJECT or ACCEPT and the Hamming
+   fast path (if asked for) did not decide. */
 uint32_t gko_filter_pair_trace(const char *read, uint32_t m, const char *ref,
                                uint64_t ref_len, uint64_t pos, uint32_t e,
                                uint32_t flags, uint16_t *est, uint8_t *masks);

@@ -139,3 +139,20 @@ def test_p3_reversal_long_reads():
         g = "".join(g)
         e = rnd.randint(0, 40)
         assert oracle.filter_pair(r, g, 0, e) == oracle.filter_pair(r[::-1], g[::-1], 0, e)
+
+
+@settings(max_examples=400, deadline=None)
+@given(pair(), st.integers(0, 12), st.sampled_from([0, oracle.NO_REFINE]))
+def test_hamming_fastpath_variant(rg, e, base):
+    """The Hamming fast path (a variant outside the paper) decides exactly the
+    pairs whose count of differing bases is at most e, accepting them with
+    that count; every other pair keeps its result without the fast path."""
+    r, g = rg
+    hd = sum(a != b for a, b in zip(r, g))
+    fast = oracle.filter_pair(r, g, 0, e, base | oracle.HAMMING_FASTPATH)
+    plain = oracle.filter_pair(r, g, 0, e, base)
+    if hd <= e:
+        assert fast == (oracle.ACCEPT, hd)
+        assert plain[0] == oracle.ACCEPT or plain[1] > hd
+    else:
+        assert fast == plain
