@@ -140,6 +140,19 @@ int gk_encode_reads(gk_ctx *ctx, const uint8_t *ascii, const uint64_t *read_off,
                     void *stream);
 
 /*
+ * Variant semantics of a batch (gk_batch.flags, gk_host_batch.flags).  The
+ * default, 0, is GateKeeper-GPU as the paper gives it.
+ * GK_FLAG_NO_REFINE: skip the leading/trailing refinement of the shifted
+ *   masks (Sec. 3.4), which gives the original GateKeeper's results.
+ * GK_FLAG_HAMMING_FASTPATH: a variant the paper does not describe: a pair
+ *   whose Hamming distance (count of differing bases) is at most e is
+ *   accepted with that count as its estimate; other pairs go through the
+ *   masks as usual.
+ */
+#define GK_FLAG_NO_REFINE        1u
+#define GK_FLAG_HAMMING_FASTPATH 2u
+
+/*
  * A batch of pairs.  All pointers are DEVICE pointers owned by the caller.
  * Pair i compares read pair_read[i] (length read_len[r]) with the reference
  * window ref[cand_pos[i], cand_pos[i] + read_len[r]) under threshold e_i
@@ -173,6 +186,9 @@ typedef struct gk_batch {
                                       bit (i mod 64) of word i/64 is 1 iff
                                       pair i is ACCEPT or UNDEFINED (i.e. it
                                       goes on to verification)               */
+    uint32_t        flags;         /* 0 (the paper's filter) or an OR of
+                                      GK_FLAG_NO_REFINE and
+                                      GK_FLAG_HAMMING_FASTPATH               */
 } gk_batch;
 
 /*
@@ -222,6 +238,7 @@ typedef struct gk_host_batch {
     uint32_t        e_uniform;     /* 0..255                                 */
     uint8_t        *accept;        /* HOST out, n_pairs                      */
     uint16_t       *est;           /* HOST out, n_pairs                      */
+    uint32_t        flags;         /* GK_FLAG_*, as gk_batch.flags           */
 } gk_host_batch;
 
 int gk_filter_host(gk_ctx *ctx, const gk_host_batch *batch);

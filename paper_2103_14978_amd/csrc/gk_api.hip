@@ -323,6 +323,8 @@ int prepare_batch(gk_ctx *ctx, const gk_batch *b, const char *who, gkd::FilterAr
         return fail(ctx, GK_EINVAL, w + ": n_reads and pitch must be below 2^30");
     if (b->read_layout != GK_READS_SPLIT && b->read_layout != GK_READS_INTERLEAVED)
         return fail(ctx, GK_EINVAL, w + ": unknown read_layout");
+    if (b->flags & ~(GK_FLAG_NO_REFINE | GK_FLAG_HAMMING_FASTPATH))
+        return fail(ctx, GK_EINVAL, w + ": unknown flags");
     if (b->n_pairs == 0)
         return 1;
     if (b->n_pairs >= (1ull << 38))
@@ -331,6 +333,7 @@ int prepare_batch(gk_ctx *ctx, const gk_batch *b, const char *who, gkd::FilterAr
         return fail(ctx, GK_EINVAL, w + ": NULL pair or output buffer");
     if (b->n_reads > 0 && (!b->reads || !b->read_len))
         return fail(ctx, GK_EINVAL, w + ": NULL read buffer");
+    a.flags = b->flags;
     a.ref_planes = ctx->ref_planes;
     a.ref_unk = ctx->ref_unk;
     a.ref_len = ctx->ref_len;
@@ -424,7 +427,7 @@ int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
 {
     if (!ctx)
         return GK_EINVAL;
-    gkd::FilterArgs a;
+    gkd::FilterArgs a{};
     int st = prepare_batch(ctx, b, "gk_filter", a);
     if (st != GK_OK)
         return st == 1 ? GK_OK : st;
@@ -483,7 +486,7 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
 {
     if (!ctx)
         return GK_EINVAL;
-    gkd::FilterArgs a;
+    gkd::FilterArgs a{};
     int st = prepare_batch(ctx, b, "gk_filter_mixed", a);
     if (st != GK_OK)
         return st == 1 ? GK_OK : st;
@@ -611,7 +614,7 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_
 {
     if (!ctx)
         return GK_EINVAL;
-    gkd::FilterArgs a;
+    gkd::FilterArgs a{};
     int st = prepare_batch(ctx, b, "gk_tune_mixed", a);
     if (st != GK_OK)
         return st == 1 ? GK_OK : st;

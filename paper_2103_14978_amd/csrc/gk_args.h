@@ -34,6 +34,7 @@ struct FilterArgs {
     uint32_t max_read_len;      // reads longer than this are GK_INVALID: the
                                 // read rows hold ceil(max_read_len/16) words
     uint32_t rows;              // ceil(max_read_len / 16)
+    uint32_t flags;             // GK_FLAG_* variant semantics (0: the paper's)
     uint32_t stream_reads;      // 1: every read and pair entry is used once
                                 // (load them non-temporally), 0: reads are
                                 // shared by several pairs (keep them cached)

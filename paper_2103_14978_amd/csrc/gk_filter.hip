@@ -15,7 +15,7 @@ namespace {
 
 // One pair per lane, no loop: the smallest register footprint (the most
 // waves per SIMD to hide the gather latency).
-template <int W, int L>
+template <int W, int L, bool VAR = false>
 __global__ __launch_bounds__(256) void k_filter_single(FilterArgs a)
 {
     const uint32_t n = (uint32_t)a.n_pairs;
@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_filter_single(FilterArgs a)
         PairData<W> d;
         load_data<W>(a, p, d);
         uint32_t est;
-        res = compute_pair<W, L>(a, p, d, est);
+        res = compute_pair<W, L, true, VAR>(a, p, d, est);
         __builtin_nontemporal_store((uint8_t)res, a.accept + i);
         __builtin_nontemporal_store((uint16_t)est, a.est + i);
     }
@@ -119,6 +119,16 @@ hipError_t launch_wl(const FilterArgs &a, uint32_t pairs_per_lane, hipStream_t s
         c.accept_bits = a.accept_bits ? a.accept_bits + first / 64 : nullptr;
         const uint64_t full = (n + 255) / 256;
         uint64_t blocks = full;
+        if (a.flags != 0u) {
+            // Variant semantics: their own one-pair-per-lane kernel, so the
+            // default kernels carry no variant code.
+            hipLaunchKernelGGL((k_filter_single<W, L, true>), dim3((uint32_t)full), dim3(256), 0,
+                               s, c);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess)
+                return e;
+            continue;
+        }
         if (pairs_per_lane == 0) {
             // Automatic: light pairs (few masks of few words) are bound by the
             // window gathers and run best with the most waves in flight; heavy

@@ -237,6 +237,7 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
             fb.max_read_len = b->max_read_len;
             fb.e_uniform = b->e_uniform;
             fb.read_layout = GK_READS_SPLIT;
+            fb.flags = b->flags;
             fb.n_pairs = q1 - q0;
             fb.cand_pos = h.cand_pos + q0;
             fb.e = b->e ? h.e + q0 : nullptr;

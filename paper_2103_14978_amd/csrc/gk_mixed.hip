@@ -53,7 +53,7 @@ struct TileOut {
     uint16_t *est;
 };
 
-template <int W, int L>
+template <int W, int L, bool VAR>
 __device__ __forceinline__ void run_chunk_pair(const FilterArgs &a, const TileOut &o,
                                                uint32_t base, uint32_t slot)
 {
@@ -61,12 +61,12 @@ __device__ __forceinline__ void run_chunk_pair(const FilterArgs &a, const TileOu
     PairData<W> d;
     load_data<W>(a, p, d);
     uint32_t est;
-    const uint32_t res = compute_pair<W, L, false>(a, p, d, est);
+    const uint32_t res = compute_pair<W, L, false, VAR>(a, p, d, est);
     o.acc[slot] = (uint8_t)res;
     o.est[slot] = (uint16_t)est;
 }
 
-template <int W, int L>
+template <int W, int L, bool VAR>
 __device__ __forceinline__ void run_chunk_pair2(const FilterArgs &a, const TileOut &o,
                                                 uint32_t base, uint32_t s0, bool has1,
                                                 uint32_t s1)
@@ -78,17 +78,17 @@ __device__ __forceinline__ void run_chunk_pair2(const FilterArgs &a, const TileO
     load_data<W>(a, p0, d0);
     load_data<W>(a, p1, d1);
     uint32_t est;
-    uint32_t res = compute_pair<W, L, false>(a, p0, d0, est);
+    uint32_t res = compute_pair<W, L, false, VAR>(a, p0, d0, est);
     o.acc[s0] = (uint8_t)res;
     o.est[s0] = (uint16_t)est;
     if (has1) {
-        res = compute_pair<W, L, false>(a, p1, d1, est);
+        res = compute_pair<W, L, false, VAR>(a, p1, d1, est);
         o.acc[s1] = (uint8_t)res;
         o.est[s1] = (uint16_t)est;
     }
 }
 
-template <int WMAX, int L, int PPL>
+template <int WMAX, int L, int PPL, bool VAR>
 __device__ __forceinline__ void run_chunk(const FilterArgs &a, const TileOut &o, uint32_t base,
                                           uint32_t w, uint32_t s0, bool has1, uint32_t s1)
 {
@@ -96,9 +96,9 @@ __device__ __forceinline__ void run_chunk(const FilterArgs &a, const TileOut &o,
     case N:                                                                        \
         if (N <= WMAX) {                                                           \
             if (PPL == 2)                                                          \
-                run_chunk_pair2<(N <= WMAX ? N : 1), L>(a, o, base, s0, has1, s1); \
+                run_chunk_pair2<(N <= WMAX ? N : 1), L, VAR>(a, o, base, s0, has1, s1); \
             else                                                                   \
-                run_chunk_pair<(N <= WMAX ? N : 1), L>(a, o, base, s0);            \
+                run_chunk_pair<(N <= WMAX ? N : 1), L, VAR>(a, o, base, s0);       \
         }                                                                          \
         break;
     switch (w) {
@@ -127,7 +127,7 @@ __device__ __forceinline__ uint32_t table_batch(const BatchTable *t, uint32_t ti
     return lo;
 }
 
-template <int WMAX, int L, int PPL>
+template <int WMAX, int L, int PPL, bool VAR = false>
 __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
 {
     extern __shared__ uint32_t lds_raw[];
@@ -272,7 +272,7 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
                 const uint32_t s0 = sorted[start + lane];
                 const bool has1 = lane + 64u < cnt;
                 const uint32_t s1 = has1 ? sorted[start + lane + 64u] : s0;
-                run_chunk<WMAX, L, PPL>(a, out, base, w, s0, has1, s1);
+                run_chunk<WMAX, L, PPL, VAR>(a, out, base, w, s0, has1, s1);
             }
         }
         __syncthreads();
@@ -288,7 +288,7 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
     }
 }
 
-template <int W, int L>
+template <int W, int L, bool VAR = false>
 __global__ __launch_bounds__(256) void k_residual(FilterArgs a0, const BatchTable *table,
                                                   uint32_t tile_size, const uint32_t *list,
                                                   const uint32_t *count)
@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void k_residual(FilterArgs a0, const BatchTabl
         PairData<W> d;
         load_data<W>(a, p, d);
         uint32_t est;
-        const uint32_t res = compute_pair<W, L, true>(a, p, d, est);
+        const uint32_t res = compute_pair<W, L, true, VAR>(a, p, d, est);
         a.accept[i] = (uint8_t)res;
         a.est[i] = (uint16_t)est;
     }
@@ -359,7 +359,16 @@ hipError_t launch_mixed_wl(const FilterArgs &a, const MixedArgs &x0, hipStream_t
         if (e != hipSuccess)
             return e;
         const uint32_t blocks = x.blocks < x.n_tiles ? x.blocks : x.n_tiles;
-        if constexpr (WMAX <= 10) {
+        if (c.flags != 0u) {
+            // Variant semantics: their own kernels, one pair per lane.
+            hipLaunchKernelGGL((k_mixed<WMAX, L, 1, true>), dim3(blocks), dim3(256),
+                               mixed_lds_bytes(x.tile), s, c, x);
+            if ((e = hipGetLastError()) != hipSuccess)
+                return e;
+            hipLaunchKernelGGL((k_residual<WMAX, L, true>), dim3(x.resid_blocks), dim3(256), 0,
+                               s, c, (const BatchTable *)nullptr, x.tile,
+                               (const uint32_t *)x.resid_list, (const uint32_t *)x.resid_count);
+        } else if constexpr (WMAX <= 10) {
             if (x.ppl == 2)
                 hipLaunchKernelGGL((k_mixed<WMAX, L, 2>), dim3(blocks), dim3(256),
                                    mixed_lds_bytes(x.tile), s, c, x);
@@ -372,9 +381,10 @@ hipError_t launch_mixed_wl(const FilterArgs &a, const MixedArgs &x0, hipStream_t
         }
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
-        hipLaunchKernelGGL((k_residual<WMAX, L>), dim3(x.resid_blocks), dim3(256), 0, s, c,
-                           (const BatchTable *)nullptr, x.tile, (const uint32_t *)x.resid_list,
-                           (const uint32_t *)x.resid_count);
+        if (c.flags == 0u)
+            hipLaunchKernelGGL((k_residual<WMAX, L>), dim3(x.resid_blocks), dim3(256), 0, s, c,
+                               (const BatchTable *)nullptr, x.tile,
+                               (const uint32_t *)x.resid_list, (const uint32_t *)x.resid_count);
         if ((e = hipGetLastError()) != hipSuccess)
             return e;
         if (a.accept_bits) {

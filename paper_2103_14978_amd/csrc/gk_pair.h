@@ -107,7 +107,7 @@ __device__ __forceinline__ void mismatch(const uint32_t (&sh)[W], const uint32_t
 // (32(W-1) < m <= 32W) and k <= 31, so the refined positions of D_k lie in
 // word 0 and those of I_k in words W-2 and W-1.  Read and window planes have
 // no bits at or beyond m.
-template <int W>
+template <int W, bool REFINE = true>
 __device__ __forceinline__ uint32_t filter_exact(const uint32_t (&rh)[W], const uint32_t (&rl)[W],
                                                  const uint32_t (&gh)[W], const uint32_t (&gl)[W],
                                                  uint32_t m, uint32_t kmax)
@@ -136,7 +136,7 @@ __device__ __forceinline__ uint32_t filter_exact(const uint32_t (&rh)[W], const 
         uint32_t Xd[W];
 #pragma unroll
         for (int w = 0; w < W; ++w)
-            Xd[w] = w == 0 ? lead : 0u;
+            Xd[w] = (REFINE && w == 0) ? lead : 0u;
         amend_and<W>(M, acc, Xd);
     }
 
@@ -155,9 +155,11 @@ __device__ __forceinline__ uint32_t filter_exact(const uint32_t (&rh)[W], const 
 #pragma unroll
         for (int w = 0; w < W; ++w)
             Xi[w] = 0u;
-        Xi[W - 1] = ~(vtop >> k);
-        if (W >= 2)
-            Xi[W >= 2 ? W - 2 : 0] = ~funnel(vtop, 0xFFFFFFFFu, k);
+        if (REFINE) {
+            Xi[W - 1] = ~(vtop >> k);
+            if (W >= 2)
+                Xi[W >= 2 ? W - 2 : 0] = ~funnel(vtop, 0xFFFFFFFFu, k);
+        }
         amend_and<W>(M, acc, Xi);
     }
 
@@ -188,7 +190,7 @@ __device__ __forceinline__ void load_read(const FilterArgs &a, uint32_t r, uint3
 // more move whole words: the read planes are shifted in place by one word each
 // time k passes a multiple of 32, and reloaded between the deletion and the
 // insertion loop.
-template <int W, int L>
+template <int W, int L, bool REFINE = true>
 __device__ __forceinline__ uint32_t filter_general(const FilterArgs &a, uint32_t r,
                                                    uint32_t (&rh)[W], uint32_t (&rl)[W],
                                                    const uint32_t (&gh)[W],
@@ -225,7 +227,7 @@ __device__ __forceinline__ uint32_t filter_general(const FilterArgs &a, uint32_t
 #pragma unroll
         for (int w = 0; w < W; ++w) {
             M[w] &= V[w];
-            X[w] = ones_below((int)k - 32 * w);
+            X[w] = REFINE ? ones_below((int)k - 32 * w) : 0u;
         }
         amend_and<W>(M, acc, X);
     }
@@ -253,7 +255,7 @@ __device__ __forceinline__ uint32_t filter_general(const FilterArgs &a, uint32_t
         mismatch<W>(sh, sl, gh, gl, M);
 #pragma unroll
         for (int w = 0; w < W; ++w)
-            X[w] = V[w] & ~ones_below((int)m - (int)k - 32 * w);
+            X[w] = REFINE ? V[w] & ~ones_below((int)m - (int)k - 32 * w) : 0u;
         amend_and<W>(M, acc, X);
     }
 
@@ -367,8 +369,10 @@ __device__ __forceinline__ void pair_planes(const PairIdx &p, const PairData<W> 
 // Filter one pair whose loads have arrived: returns the result code and sets
 // est (GK_EST_NONE unless REJECT / ACCEPT).  With GENERAL false the caller
 // guarantees 32(W-1) < m <= 32W and min(e, m-1) <= 31 for every valid pair,
-// and only the register-light fast path is compiled.
-template <int W, int L, bool GENERAL = true>
+// and only the register-light fast path is compiled.  VAR compiles the
+// variant semantics of a.flags (GK_FLAG_*); without it a.flags must be 0, and
+// the paper's filter is the only code in the kernel.
+template <int W, int L, bool GENERAL = true, bool VAR = false>
 __device__ __forceinline__ uint32_t compute_pair(const FilterArgs &a, const PairIdx &p,
                                                  const PairData<W> &d, uint32_t &est)
 {
@@ -380,14 +384,32 @@ __device__ __forceinline__ uint32_t compute_pair(const FilterArgs &a, const Pair
     uint32_t gh[W], gl[W], rh[W], rl[W];
     pair_planes<W, L>(p, d, m, gh, gl, rh, rl);
     const uint32_t kmax = p.e < m - 1u ? p.e : m - 1u;
-    if (!GENERAL || (m > 32u * (W - 1) && kmax <= 31u)) {
+    const bool exact = !GENERAL || (m > 32u * (W - 1) && kmax <= 31u);
+    if (exact) {
         const uint32_t vtop = ones_below((int)m - 32 * (W - 1));
         rh[W - 1] &= vtop;
         rl[W - 1] &= vtop;
-        est = filter_exact<W>(rh, rl, gh, gl, m, kmax);
-    } else {
-        est = filter_general<W, L>(a, p.r, rh, rl, gh, gl, m, kmax);
     }
+    if constexpr (VAR) {                       // variants (uniform per launch)
+        if (a.flags & GK_FLAG_HAMMING_FASTPATH) {
+            uint32_t hd = 0;
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                hd += __builtin_popcount(((rh[w] ^ gh[w]) | (rl[w] ^ gl[w])) &
+                                         ones_below((int)m - 32 * w));
+            if (hd <= p.e) {
+                est = hd;
+                return GK_ACCEPT;
+            }
+        }
+        if (a.flags & GK_FLAG_NO_REFINE) {
+            est = exact ? filter_exact<W, false>(rh, rl, gh, gl, m, kmax)
+                        : filter_general<W, L, false>(a, p.r, rh, rl, gh, gl, m, kmax);
+            return est <= p.e ? GK_ACCEPT : GK_REJECT;
+        }
+    }
+    est = exact ? filter_exact<W>(rh, rl, gh, gl, m, kmax)
+                : filter_general<W, L>(a, p.r, rh, rl, gh, gl, m, kmax);
     return est <= p.e ? GK_ACCEPT : GK_REJECT;
 }
 

@@ -87,14 +87,14 @@ def upload_pairs(pair_read: np.ndarray | None, cand_pos: np.ndarray, e: np.ndarr
 
 
 def batch_for(reads: DeviceReads, pairs: DevicePairs, *, e_uniform: int = 0,
-              max_read_len: int | None = None) -> gk.gk_batch:
+              max_read_len: int | None = None, flags: int = 0) -> gk.gk_batch:
     return gk.make_batch(
         n_reads=reads.n_reads, pitch=reads.pitch,
         max_read_len=max_read_len if max_read_len is not None else reads.max_len,
         reads=reads.packed, read_len=reads.read_len, read_has_n=reads.has_n,
         n_pairs=pairs.n_pairs, pair_read=pairs.pair_read, cand_pos=pairs.cand_pos,
         e=pairs.e, e_uniform=e_uniform, accept=pairs.accept, est=pairs.est,
-        accept_bits=pairs.accept_bits, read_layout=reads.layout)
+        accept_bits=pairs.accept_bits, read_layout=reads.layout, flags=flags)
 
 
 def results(pairs: DevicePairs) -> tuple[np.ndarray, np.ndarray]:

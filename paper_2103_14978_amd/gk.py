@@ -22,6 +22,8 @@ GK_SERVER_BATCHED, GK_SERVER_SEQUENTIAL = 0, 1
 GK_REJECT, GK_ACCEPT, GK_UNDEFINED, GK_INVALID = 0, 1, 2, 3
 GK_EST_NONE = 0xFFFF
 GK_VERIFY_MAX_E = 31
+GK_FLAG_NO_REFINE = 1
+GK_FLAG_HAMMING_FASTPATH = 2
 GK_MAX_READ_LEN = 512
 GK_READS_SPLIT, GK_READS_INTERLEAVED = 0, 1
 GK_OPT_PAIRS_PER_LANE = 1
@@ -57,6 +59,7 @@ class gk_batch(ctypes.Structure):
         ("accept", ctypes.c_void_p),
         ("est", ctypes.c_void_p),
         ("accept_bits", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
     ]
 
 
@@ -73,6 +76,7 @@ class gk_host_batch(ctypes.Structure):
         ("e_uniform", ctypes.c_uint32),
         ("accept", ctypes.c_void_p),
         ("est", ctypes.c_void_p),
+        ("flags", ctypes.c_uint32),
     ]
 
 
@@ -160,7 +164,8 @@ def lib() -> ctypes.CDLL:
 
 
 EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
-            "gk_load_reference_2bit", "gk_reference_info", "gk_encode_reads", "gk_filter", "gk_filter_host", "gk_verify", "gk_set_option",
+            "gk_load_reference_2bit", "gk_reference_info", "gk_encode_reads", "gk_filter",
+            "gk_filter_host", "gk_verify", "gk_set_option",
             "gk_get_option", "gk_filter_mixed", "gk_tune_mixed", "gk_server_start",
             "gk_server_submit", "gk_server_wait", "gk_server_counters", "gk_server_stop",
             "gk_clock_us")
@@ -262,8 +267,9 @@ def gk_get_option(ctx, option: int) -> int:
 
 def make_batch(*, n_reads, pitch, max_read_len, reads, read_len, pair_read, cand_pos, accept,
                est, n_pairs=None, e=None, e_uniform=0, read_has_n=None, accept_bits=None,
-               read_layout=GK_READS_SPLIT) -> gk_batch:
+               read_layout=GK_READS_SPLIT, flags=0) -> gk_batch:
     b = gk_batch()
+    b.flags = flags
     b.n_reads = n_reads
     b.pitch = pitch
     b.max_read_len = max_read_len
@@ -300,7 +306,7 @@ def host_ptr(x):
 
 def gk_filter_host(ctx, ascii, read_off, cand_pos, accept, est, *, max_read_len: int,
                    pair_read=None, e=None, e_uniform: int = 0, n_reads=None,
-                   n_pairs=None) -> None:
+                   n_pairs=None, flags: int = 0) -> None:
     """Host buffers in, host results out (synchronous).  Arrays are
     contiguous numpy arrays of the ABI's dtypes, or CPU torch tensors (e.g.
     pinned byte buffers) with n_reads and n_pairs given."""
@@ -312,7 +318,7 @@ def gk_filter_host(ctx, ascii, read_off, cand_pos, accept, est, *, max_read_len:
                       read_off=host_ptr(read_off), n_pairs=n_pairs,
                       pair_read=host_ptr(pair_read), cand_pos=host_ptr(cand_pos),
                       e=host_ptr(e), e_uniform=e_uniform, accept=host_ptr(accept),
-                      est=host_ptr(est))
+                      est=host_ptr(est), flags=flags)
     _check(ctx, lib().gk_filter_host(ctx, ctypes.byref(b)), "gk_filter_host")
 
 
