@@ -115,26 +115,53 @@ __global__ __launch_bounds__(256) void k_verify(FilterArgs a, const uint32_t *li
 __global__ void k_verify_reset(uint32_t *count) { *count = 0u; }
 
 // Lists the pairs to verify (accept[i] == GK_ACCEPT, or every pair when
-// accept is NULL) with one atomic per wave; the rest get GK_EST_NONE.
+// accept is NULL) in pair order within each workgroup's contiguous range, with
+// one atomic per workgroup: a first pass counts the range's selected pairs, a
+// second writes them.  The other pairs get GK_EST_NONE.
 __global__ __launch_bounds__(256) void k_verify_select(const uint8_t *accept, uint32_t n,
                                                        uint32_t *list, uint32_t *count,
                                                        uint16_t *dist)
 {
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t stride = gridDim.x * 256u;
-    for (uint32_t base = blockIdx.x * 256u + (threadIdx.x & ~63u); base < n; base += stride) {
-        const uint32_t i = base + lane;
-        const bool in = i < n;
-        const bool sel = in && (accept == nullptr || accept[i] == GK_ACCEPT);
-        if (in && !sel)
+    __shared__ uint32_t wave_sum[4];
+    __shared__ uint32_t base;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t per = ((n + gridDim.x - 1) / gridDim.x + 255u) & ~255u;
+    const uint32_t lo = blockIdx.x * per;
+    const uint32_t hi = lo + per < n ? lo + per : n;
+
+    uint32_t c = 0;
+    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256u) {
+        const bool sel = accept == nullptr || accept[i] == GK_ACCEPT;
+        c += sel ? 1u : 0u;
+        if (!sel)
             dist[i] = (uint16_t)GK_EST_NONE;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        c += __shfl_xor(c, o, 64);
+    if (lane == 0u)
+        wave_sum[wave] = c;
+    __syncthreads();
+    if (threadIdx.x == 0u) {
+        const uint32_t total = wave_sum[0] + wave_sum[1] + wave_sum[2] + wave_sum[3];
+        base = total ? atomicAdd(count, total) : 0u;
+    }
+    __syncthreads();
+    uint32_t run = base;
+    for (uint32_t start = lo; start < hi; start += 256u) {     // uniform per block
+        const uint32_t i = start + threadIdx.x;
+        const bool sel = i < hi && (accept == nullptr || accept[i] == GK_ACCEPT);
         const unsigned long long mask = __ballot(sel);
-        uint32_t first = 0;
-        if (lane == 0u && mask)
-            first = atomicAdd(count, (uint32_t)__popcll(mask));
-        first = __shfl(first, 0, 64);
+        __syncthreads();                 // wave_sum of the previous step is read
+        if (lane == 0u)
+            wave_sum[wave] = (uint32_t)__popcll(mask);
+        __syncthreads();
+        uint32_t before = 0;
+        for (uint32_t w = 0; w < wave; ++w)
+            before += wave_sum[w];
         if (sel)
-            list[first + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = i;
+            list[run + before + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = i;
+        run += wave_sum[0] + wave_sum[1] + wave_sum[2] + wave_sum[3];
     }
 }
 
@@ -165,7 +192,7 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
         uint16_t *out = dist + first;
         hipLaunchKernelGGL(k_verify_reset, dim3(1), dim3(1), 0, s, count);
         const uint64_t want = (n + 255) / 256;
-        const uint32_t sel_blocks = (uint32_t)(want < (uint64_t)cus * 16 ? want : (uint64_t)cus * 16);
+        const uint32_t sel_blocks = (uint32_t)(want < (uint64_t)cus * 4 ? want : (uint64_t)cus * 4);
         hipLaunchKernelGGL(k_verify_select, dim3(sel_blocks), dim3(256), 0, s, acc, (uint32_t)n,
                            list, count, out);
         const uint64_t vb = want < (uint64_t)cus * per_cu ? want : (uint64_t)cus * per_cu;

@@ -3,8 +3,8 @@
 
 For each workload and threshold e, on a seeded sample of its pairs, the
 oracle filters every pair (with the GPU version's leading/trailing
-refinement of Sec. 3.4, and without it, which is the GateKeeper-FPGA
-behaviour) and the banded Levenshtein distance (unit-cost global alignment
+refinement of Sec. 3.4; without it, which is the GateKeeper-FPGA behaviour;
+and with the Hamming fast path, a variant the paper does not describe) and the banded Levenshtein distance (unit-cost global alignment
 of the read and its window, capped at e + 1) decides which pairs truly lie
 within e edits.  As in Sec. 4.4 and Sec. 5.1:
     FA = accepted although lev > e,   FA rate = FA / #(lev > e)
@@ -30,6 +30,7 @@ import gen      # noqa: E402
 import oracle   # noqa: E402
 
 NO_REFINE = 1
+HAMMING = 2
 
 
 def row(label, ref, ps, e, threads):
@@ -39,6 +40,8 @@ def row(label, ref, ps, e, threads):
                                n_threads=threads)
     a0, _ = oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read, ps.cand_pos, e,
                                 flags=NO_REFINE, n_threads=threads)
+    ah, _ = oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read, ps.cand_pos, e,
+                                flags=HAMMING, n_threads=threads)
     lev = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read, ps.cand_pos, cap,
                                    n_threads=threads).astype(np.int64)
     ee = e_arr.astype(np.int64) if e_arr is not None else int(e)
@@ -49,13 +52,15 @@ def row(label, ref, ps, e, threads):
     fr = int(np.sum(within & (a == 0)))
     fa0 = int(np.sum(beyond & (a0 == 1)))
     fr0 = int(np.sum(within & (a0 == 0)))
+    fah = int(np.sum(beyond & (ah == 1)))
+    frh = int(np.sum(within & (ah == 0)))
     nb, nw = int(beyond.sum()), int(within.sum())
 
     def rate(x, n):
         return f"{x / n:.4f}" if n else "-"
     return (f"| {label} | {ps.n_pairs} | {int((~defined).sum())} | {nw} | {nb} | "
             f"{fa} ({rate(fa, nb)}) | {fr} ({rate(fr, nw)}) | {fa0} ({rate(fa0, nb)}) | "
-            f"{fr0} ({rate(fr0, nw)}) |")
+            f"{fr0} ({rate(fr0, nw)}) | {fah} ({rate(fah, nb)}) | {frh} ({rate(frh, nw)}) |")
 
 
 def main():
@@ -66,8 +71,9 @@ def main():
     n, th = args.sample, args.threads
     t0 = time.time()
     print("| workload | pairs | undefined | lev <= e | lev > e | FA (rate) | FR (rate) | "
-          "FA without refinement | FR without refinement |")
-    print("|---|---|---|---|---|---|---|---|---|")
+          "FA without refinement | FR without refinement | FA with Hamming fast path | "
+          "FR with Hamming fast path |")
+    print("|---|---|---|---|---|---|---|---|---|---|---|")
     ref0 = gen.c0_reference()
     ps = gen.c0_pairs(ref0)
     for e in (0, 1, 2, 3, 5):

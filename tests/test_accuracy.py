@@ -61,3 +61,16 @@ def test_sparse_substitutions_are_accepted(c0, e):
         assert est[i] <= len(r)
         if len(diff) <= e and (len(diff) < 2 or np.min(np.diff(diff)) >= 4):
             assert a[i] == 1 and est[i] <= len(diff), i
+
+
+@pytest.mark.parametrize("e", [1, 2, 3, 5])
+def test_hamming_fastpath_adds_no_false_accept(c0, e):
+    """Edit distance never exceeds Hamming distance for equal lengths, so the
+    Hamming fast path (a variant outside the paper) cannot add a false accept;
+    it only turns rejects into accepts, so it never adds a false reject."""
+    ref, ps = c0
+    a, _, lev = counts(ref, ps, e)
+    ah, _, _ = counts(ref, ps, e, oracle.HAMMING_FASTPATH)
+    assert np.sum((ah == 1) & (lev > e)) == np.sum((a == 1) & (lev > e))
+    assert np.sum((ah == 0) & (lev <= e)) <= np.sum((a == 0) & (lev <= e))
+    assert np.all(ah[a == 1] == 1)
