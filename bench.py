@@ -122,8 +122,9 @@ def main() -> int:
     ap.add_argument("--slo-ms", type=float, default=25.0, help="served: p99 target")
     ap.add_argument("--pageable", action="store_true",
                     help="served: keep requests in pageable host memory (default: pinned)")
-    ap.add_argument("--tune-sample", type=int, default=1 << 23,
-                    help="mixed: pairs the autotuner times each candidate on")
+    ap.add_argument("--tune-sample", type=int, default=1 << 26,
+                    help="mixed: pairs the autotuner times each candidate on (the whole "
+                         "batch by default: smaller samples have misranked close candidates)")
     ap.add_argument("--mixed-config", default=None,
                     help="mixed: fixed tuning 'tile,ppl,sort_e,blocks_per_cu' instead of "
                          "the autotuner")

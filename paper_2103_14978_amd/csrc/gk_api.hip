@@ -33,9 +33,25 @@ void free_reference(gk_ctx *ctx)
         (void)hipFree(ctx->ref_planes);
     if (ctx->ref_unk)
         (void)hipFree(ctx->ref_unk);
+    if (ctx->ref_planes_b)
+        (void)hipFree(ctx->ref_planes_b);
+    ctx->ref_planes_b = nullptr;
     ctx->ref_planes = nullptr;
     ctx->ref_unk = nullptr;
     ctx->ref_len = ctx->ref_words = ctx->ref_unknown = 0;
+}
+
+// The shifted copy of the resident planes (see gkd::REF_SHIFT_WORDS).
+hipError_t make_shifted_planes(gk_ctx *ctx, uint64_t alloc_words)
+{
+    const uint64_t k = gkd::REF_SHIFT_WORDS;
+    hipError_t e = hipMalloc(&ctx->ref_planes_b, alloc_words * sizeof(uint2));
+    if (e == hipSuccess)
+        e = hipMemset(ctx->ref_planes_b + (alloc_words - k), 0, k * sizeof(uint2));
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->ref_planes_b, ctx->ref_planes + k, (alloc_words - k) * sizeof(uint2),
+                      hipMemcpyDeviceToDevice);
+    return e;
 }
 
 }  // namespace
@@ -165,6 +181,8 @@ int gk_load_reference(gk_ctx *ctx, const char *ascii, uint64_t len)
     if (e == hipSuccess)
         e = hipMemcpy(&unknown, ctx->d_counter, sizeof unknown, hipMemcpyDeviceToHost);
     (void)hipFree(stage);
+    if (e == hipSuccess)
+        e = make_shifted_planes(ctx, alloc_words);
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference: pack");
     ctx->ref_len = len;
@@ -250,6 +268,8 @@ int gk_load_reference_2bit(gk_ctx *ctx, const uint32_t *packed, uint64_t len, ui
     unsigned long long unknown = 0;
     if (e == hipSuccess)
         e = hipMemcpy(&unknown, ctx->d_counter, sizeof unknown, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        e = make_shifted_planes(ctx, alloc_words);
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: unpack");
     ctx->ref_len = len;
@@ -335,6 +355,7 @@ int prepare_batch(gk_ctx *ctx, const gk_batch *b, const char *who, gkd::FilterAr
         return fail(ctx, GK_EINVAL, w + ": NULL read buffer");
     a.flags = b->flags;
     a.ref_planes = ctx->ref_planes;
+    a.ref_planes_b = ctx->ref_planes_b;
     a.ref_unk = ctx->ref_unk;
     a.ref_len = ctx->ref_len;
     a.ref_has_unknown = ctx->ref_unknown > 0;

@@ -23,8 +23,16 @@ constexpr uint32_t MAX_WORDS = GK_MAX_READ_LEN / 32;  // 32-base words per mask
 constexpr uint32_t GK_PPL_RESIDENT = 65536;  // pairs-per-lane value meaning
                                              // "one residency of the device"
 
+// Second copy of the planes, shifted by half a 128-byte cache line:
+// ref_planes_b[j] = ref_planes[j + REF_SHIFT_WORDS].  A window gather of up to
+// 9 words that crosses a line of ref_planes lies within one line of
+// ref_planes_b, so every window of up to 256 bases costs one line fetch.
+constexpr uint32_t LINE_WORDS = 16;          // uint2 words per 128-byte line
+constexpr uint32_t REF_SHIFT_WORDS = 8;
+
 struct FilterArgs {
     const uint2 *ref_planes;
+    const uint2 *ref_planes_b;  // ref_planes shifted by REF_SHIFT_WORDS, or NULL
     const uint32_t *ref_unk;
     uint64_t ref_len;
     uint32_t ref_has_unknown;

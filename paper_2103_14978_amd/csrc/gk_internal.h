@@ -45,6 +45,7 @@ struct gk_ctx {
     uint64_t ref_words = 0;     // ceil(ref_len / 32)
     uint64_t ref_unknown = 0;   // unknown bases
     uint2 *ref_planes = nullptr;
+    uint2 *ref_planes_b = nullptr;            // planes shifted by half a line
     uint32_t *ref_unk = nullptr;
     unsigned long long *d_counter = nullptr;  // scratch for the unknown count
     uint32_t pairs_per_lane = 0;              // GK_OPT_PAIRS_PER_LANE

@@ -310,9 +310,14 @@ __device__ __forceinline__ void load_data(const FilterArgs &a, const PairIdx &p,
         const uint32_t *row = a.reads + (size_t)j * a.pitch;
         d.words[j] = (a.n_reads && (uint32_t)j < a.rows) ? ld_once(a, row + r) : 0u;
     }
-    // Only the words a window of up to max_read_len bases can touch.
-    const uint2 *src = a.ref_planes + (pos >> 5);
+    // Only the words a window of up to max_read_len bases can touch, from the
+    // copy of the planes in which they share one 128-byte line.
+    const uint32_t w0 = pos >> 5;
     const uint32_t span = (pos & 31u) + a.max_read_len;
+    const uint32_t nw = (span + 31u) >> 5;
+    const bool use_b = a.ref_planes_b != nullptr && w0 >= REF_SHIFT_WORDS &&
+                       (w0 & (LINE_WORDS - 1u)) + nw > LINE_WORDS;
+    const uint2 *src = use_b ? a.ref_planes_b + (w0 - REF_SHIFT_WORDS) : a.ref_planes + w0;
 #pragma unroll
     for (int w = 0; w <= W; ++w)
         d.win[w] = 32u * w < span ? src[w] : make_uint2(0u, 0u);

@@ -125,6 +125,8 @@ struct gk_server {
     Arena arena;
     uint8_t *d_arena = nullptr;
     hipStream_t s_copy = nullptr, s_compute = nullptr, s_d2h = nullptr;
+    hipStream_t s_copy2 = nullptr;         // batched mode: every other request
+    uint64_t admitted = 0;                 // requests admitted so far
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Req *> pending, ready;
@@ -204,6 +206,7 @@ gkd::FilterArgs args_for(const gk_server *s, const Req *q)
     const gk_ctx *c = s->ctx;
     gkd::FilterArgs a{};
     a.ref_planes = c->ref_planes;
+    a.ref_planes_b = c->ref_planes_b;
     a.ref_unk = c->ref_unk;
     a.ref_len = c->ref_len;
     a.ref_has_unknown = c->ref_unknown > 0;
@@ -322,7 +325,12 @@ void loader_main(gk_server *s)
         place(s, q);
         lk.unlock();
 
-        hipError_t e = load_request(s, q, s->s_copy);
+        // Batched mode alternates two copy streams, so one request's
+        // transfers and encoding overlap the next one's.
+        hipStream_t st = s->s_copy;
+        if (s->mode == GK_SERVER_BATCHED && (s->admitted++ & 1u))
+            st = s->s_copy2;
+        hipError_t e = load_request(s, q, st);
         if (s->mode == GK_SERVER_SEQUENTIAL) {
             // One request at a time on one stream: copy in, encode, filter, copy out.
             if (e == hipSuccess) {
@@ -344,7 +352,7 @@ void loader_main(gk_server *s)
             continue;
         }
         if (e == hipSuccess)
-            e = hipEventRecord(q->ready, s->s_copy);
+            e = hipEventRecord(q->ready, st);
         lk.lock();
         if (e != hipSuccess) {
             finish(s, q, GK_EDEVICE);
@@ -469,7 +477,7 @@ void destroy_server(gk_server *s)
         (void)hipFree(s->d_counters);
     if (s->d_resid)
         (void)hipFree(s->d_resid);
-    for (hipStream_t st : {s->s_copy, s->s_compute, s->s_d2h})
+    for (hipStream_t st : {s->s_copy, s->s_copy2, s->s_compute, s->s_d2h})
         if (st)
             (void)hipStreamDestroy(st);
     delete s;
@@ -507,7 +515,7 @@ int gk_server_start(gk_ctx *ctx, uint64_t device_budget_bytes, uint32_t max_slot
     s->budget = device_budget_bytes;
     s->arena.init(device_budget_bytes);
     hipError_t e = hipMalloc(&s->d_arena, device_budget_bytes);
-    for (hipStream_t *st : {&s->s_copy, &s->s_compute, &s->s_d2h})
+    for (hipStream_t *st : {&s->s_copy, &s->s_copy2, &s->s_compute, &s->s_d2h})
         if (e == hipSuccess)
             e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
     if (e == hipSuccess)
