@@ -594,6 +594,7 @@ def bench_served(args, log) -> int:
             done = []
             outs = {}
             lag = []          # submitter lateness: actual submit - scheduled arrival
+            parts = []        # (admission wait, service time) per finished request
             t0 = gk.gk_clock_us() + 200_000
             arrivals = t0 + (np.cumsum(gaps) * 1e6).astype(np.int64)
 
@@ -633,6 +634,8 @@ def bench_served(args, log) -> int:
                 if st == gk.GK_ETIMEOUT:
                     break
                 done.append((stats.t_done_us - stats.t_submit_us, stats.n_pairs))
+                parts.append((stats.t_admit_us - stats.t_submit_us,
+                              stats.t_done_us - stats.t_admit_us))
                 w = int(which[k])
                 if w in checked:
                     ra, rs = checked[w]
@@ -658,7 +661,11 @@ def bench_served(args, log) -> int:
                    "pairs_per_s": round(float(sum(n for _, n in done)) / span, 1),
                    "ticks": ticks, "max_requests_per_tick": per_tick,
                    "submit_lag_p99_ms": round(float(np.percentile(lag, 99)) / 1e3, 3)
-                   if lag else None}
+                   if lag else None,
+                   "admit_wait_p99_ms": round(float(np.percentile([a for a, _ in parts], 99))
+                                              / 1e3, 3) if parts else None,
+                   "service_p99_ms": round(float(np.percentile([b for _, b in parts], 99))
+                                           / 1e3, 3) if parts else None}
             results[mode_name].append(rec)
             log(f"{mode_name} lambda={lam}: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms, "
                 f"{rec['pairs_per_s'] / 1e6:.1f} M pairs/s, unfinished {unfinished}")

@@ -433,6 +433,16 @@ void completer_main(gk_server *s)
         Tick t = s->inflight.front();
         lk.unlock();
         hipError_t e = hipEventSynchronize(s->tick_done[t.buf]);
+        const bool released = e == hipSuccess;
+        if (released) {
+            // The tick's kernels are done with its table: the scheduler may
+            // launch the next tick into this buffer while the results are
+            // copied out (so the buffer must not be released again below).
+            lk.lock();
+            s->buf_busy[t.buf] = false;
+            s->cv.notify_all();
+            lk.unlock();
+        }
         for (auto *q : t.reqs)
             if (e == hipSuccess)
                 e = copy_out(q, s->s_d2h);
@@ -444,7 +454,8 @@ void completer_main(gk_server *s)
         s->inflight.pop_front();
         for (auto *q : t.reqs)
             finish(s, q, e == hipSuccess ? GK_OK : GK_EDEVICE);
-        s->buf_busy[t.buf] = false;
+        if (!released)
+            s->buf_busy[t.buf] = false;
         if (e != hipSuccess) {
             fail_all(s, std::string("server copy out: ") + hipGetErrorName(e));
             break;
