@@ -125,3 +125,35 @@ def test_verify_after_filter_and_status(gkctx):
     e = np.array([3, 3, 3, 3, 3], np.uint8)
     d = verify(gkctx, reads, off, pr, pos, e, 128)
     assert list(d) == [0] + [gk.GK_EST_NONE] * 4
+
+
+def test_verify_errors(gkctx):
+    """Call errors: a NULL dist, no reference, bad arguments; an empty batch
+    is a no-op."""
+    ref = gen.c0_reference()
+    gk.gk_load_reference(gkctx, ref)
+    reads, off = concat_reads([ref[10:110].tobytes()])
+    dr = device.encode_reads(gkctx, reads, off, max_len=100)
+    dp = device.upload_pairs(np.array([0], np.uint32), np.array([10], np.uint32))
+    b = device.batch_for(dr, dp, e_uniform=2, max_read_len=100)
+    with pytest.raises(gk.GkError) as ei:
+        gk.gk_verify(gkctx, b, None, None, None)
+    assert ei.value.status == gk.GK_EINVAL and "dist" in str(ei.value)
+    dist = torch.empty(1, dtype=torch.int16, device="cuda")
+    bad = device.batch_for(dr, dp, e_uniform=2, max_read_len=600)
+    with pytest.raises(gk.GkError) as ei:
+        gk.gk_verify(gkctx, bad, None, dist, None)
+    assert ei.value.status == gk.GK_EINVAL
+    ctx2 = gk.gk_create(0)
+    try:
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_verify(ctx2, b, None, dist, None)
+        assert ei.value.status == gk.GK_ENOREF
+    finally:
+        gk.gk_destroy(ctx2)
+    b.n_pairs = 0
+    gk.gk_verify(gkctx, b, None, None, None)      # empty: nothing to check
+    b.n_pairs = 1
+    gk.gk_verify(gkctx, b, None, dist, None)
+    torch.cuda.synchronize()
+    assert int(dist.cpu().numpy().view(np.uint16)[0]) == 0
