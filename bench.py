@@ -678,11 +678,16 @@ def bench_served(args, log) -> int:
                 f"{rec['pairs_per_s'] / 1e6:.1f} M pairs/s, unfinished {unfinished}")
 
     def at_slo(rows):
-        ok = [r for r in rows if r["p99_ms"] is not None and r["p99_ms"] <= args.slo_ms
-              and r["unfinished"] == 0]
-        if not ok:
+        """The highest rate below the first one that misses the SLO (a later
+        rate that happens to meet it again does not count)."""
+        best = None
+        for r in sorted(rows, key=lambda r: r["lambda"]):
+            if ("p99_ms" not in r or r["p99_ms"] is None or r["p99_ms"] > args.slo_ms
+                    or r["unfinished"] != 0):
+                break
+            best = r
+        if best is None:
             return None
-        best = max(ok, key=lambda r: r["lambda"])
         return {"lambda": best["lambda"], "pairs_per_s": best["pairs_per_s"],
                 "p99_ms": best["p99_ms"]}
 

@@ -25,30 +25,44 @@
 namespace gkd {
 namespace {
 
+// One column step of the banded edit distance.  bh, bl: the band's read-plane
+// bits (bit k = read base j - e + k - 1, 0-based, for text column j); th, tl:
+// the text base's code bits as all-zero / all-one masks.
 template <typename T>
-__device__ __forceinline__ T widen_mask(uint32_t x)
+__device__ __forceinline__ void band_step(T bh, T bl, T th, T tl, T top, T keep, uint32_t e,
+                                          T &vp, T &vn, uint32_t &score)
 {
-    return (T)(int32_t)x;   // 0 or all ones
+    const T eq = ~((bh ^ th) | (bl ^ tl));
+    // slide the band down one row; the new bottom row steps +1
+    vp = ((vp >> 1) & keep) | top;
+    vn = (vn >> 1) & keep;
+    const T xv = eq | vn;
+    const T xh = (((eq & vp) + vp) ^ vp) | eq;
+    score += 1u - (uint32_t)(((xh | vn) >> e) & 1u);   // diagonal step
+    T ph = vn | ~(xh | vp);
+    T mh = vp & xh;
+    ph = (ph << 1) | 1u;                 // the row above the band steps +1
+    mh = mh << 1;
+    vp = mh | ~(xv | ph);
+    vn = ph & xv;
 }
 
-// 32 (T = uint32_t) or 64 (T = uint64_t) read-plane bits starting at extended
-// bit x' = 32 blk + c + 32 - e of [32 zero bits | plane words 0..W-1 | zeros]:
-// band bit k holds read base j - e + k - 1 (0-based) for text column
-// j = 32 blk + c + 1.
+// 32 (T = uint32_t) or 64 (T = uint64_t) bits of [a | b | c] from bit s of a.
 template <typename T>
-__device__ __forceinline__ T band_bits(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3,
-                                       bool upper, uint32_t s)
+__device__ __forceinline__ T bits_from(uint32_t a, uint32_t b, uint32_t c, uint32_t s)
 {
-    const uint32_t a = upper ? w1 : w0, b = upper ? w2 : w1;
     const uint32_t lo = funnel(b, a, s);
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4)
         return lo;
-    } else {
-        const uint32_t c = upper ? w3 : w2;
+    else
         return ((uint64_t)funnel(c, b, s) << 32) | lo;
-    }
 }
 
+// Read bases are taken from [32 zero bits | plane words 0..W-1 | zeros]: for
+// text column j = 32 blk + c + 1 the band starts at extended bit
+// 32 blk + c + 32 - e, which lies in extended word blk (read word blk - 1)
+// while c < e and in word blk + 1 (read word blk) from c = e on; the column
+// loop is split there so each part reads fixed words.
 template <int W, typename T>
 __device__ __forceinline__ uint32_t band_distance(const uint32_t (&rh)[W], const uint32_t (&rl)[W],
                                                   const uint32_t (&gh)[W], const uint32_t (&gl)[W],
@@ -66,26 +80,21 @@ __device__ __forceinline__ uint32_t band_distance(const uint32_t (&rh)[W], const
         const uint32_t h2 = blk + 1 < W ? rh[blk + 1] : 0u, l2 = blk + 1 < W ? rl[blk + 1] : 0u;
         const uint32_t h3 = blk + 2 < W ? rh[blk + 2] : 0u, l3 = blk + 2 < W ? rl[blk + 2] : 0u;
         const int cols = (int)m - 32 * blk < 32 ? (int)m - 32 * blk : 32;
-        for (int c = 0; c < cols; ++c) {
-            const bool upper = (uint32_t)c >= e;
-            const uint32_t s = ((uint32_t)c - e) & 31u;
-            const T bh = band_bits<T>(h0, h1, h2, h3, upper, s);
-            const T bl = band_bits<T>(l0, l1, l2, l3, upper, s);
-            const T th = widen_mask<T>(__builtin_amdgcn_sbfe(gh[blk], c, 1));
-            const T tl = widen_mask<T>(__builtin_amdgcn_sbfe(gl[blk], c, 1));
-            const T eq = ~((bh ^ th) | (bl ^ tl));
-            // slide the band down one row; the new bottom row steps +1
-            vp = ((vp >> 1) & keep) | top;
-            vn = (vn >> 1) & keep;
-            const T xv = eq | vn;
-            const T xh = (((eq & vp) + vp) ^ vp) | eq;
-            score += 1u - (uint32_t)(((xh | vn) >> e) & 1u);   // diagonal step
-            T ph = vn | ~(xh | vp);
-            T mh = vp & xh;
-            ph = (ph << 1) | 1u;                 // the row above the band steps +1
-            mh = mh << 1;
-            vp = mh | ~(xv | ph);
-            vn = ph & xv;
+        const int split = (int)e < cols ? (int)e : cols;
+        const uint32_t th_w = gh[blk], tl_w = gl[blk];
+        for (int c = 0; c < split; ++c) {          // band starts in read word blk - 1
+            const uint32_t s = (uint32_t)c + 32u - e;
+            band_step<T>(bits_from<T>(h0, h1, h2, s), bits_from<T>(l0, l1, l2, s),
+                         (T)(int32_t)__builtin_amdgcn_sbfe(th_w, c, 1),
+                         (T)(int32_t)__builtin_amdgcn_sbfe(tl_w, c, 1), top, keep, e, vp, vn,
+                         score);
+        }
+        for (int c = split; c < cols; ++c) {       // band starts in read word blk
+            const uint32_t s = (uint32_t)c - e;
+            band_step<T>(bits_from<T>(h1, h2, h3, s), bits_from<T>(l1, l2, l3, s),
+                         (T)(int32_t)__builtin_amdgcn_sbfe(th_w, c, 1),
+                         (T)(int32_t)__builtin_amdgcn_sbfe(tl_w, c, 1), top, keep, e, vp, vn,
+                         score);
         }
     }
     return score < e + 1u ? score : e + 1u;
