@@ -36,13 +36,20 @@ void free_reference(gk_ctx *ctx)
     if (ctx->ref_planes_b)
         (void)hipFree(ctx->ref_planes_b);
     ctx->ref_planes_b = nullptr;
+    if (ctx->ref_unk_lines)
+        (void)hipFree(ctx->ref_unk_lines);
+    ctx->ref_unk_lines = nullptr;
     ctx->ref_planes = nullptr;
     ctx->ref_unk = nullptr;
     ctx->ref_len = ctx->ref_words = ctx->ref_unknown = 0;
 }
 
-// The shifted copy of the resident planes (see gkd::REF_SHIFT_WORDS).
-hipError_t make_shifted_planes(gk_ctx *ctx, uint64_t alloc_words)
+// Derived views of a loaded reference: the shifted copy of the planes (see
+// gkd::REF_SHIFT_WORDS) and the one-bit-per-line summary of the unknown plane,
+// which lets a pair skip the unknown-plane gather when its window's lines
+// hold no unknown base.
+hipError_t finish_reference(gk_ctx *ctx, uint64_t words, uint64_t alloc_words,
+                            uint64_t unknown)
 {
     const uint64_t k = gkd::REF_SHIFT_WORDS;
     hipError_t e = hipMalloc(&ctx->ref_planes_b, alloc_words * sizeof(uint2));
@@ -51,6 +58,15 @@ hipError_t make_shifted_planes(gk_ctx *ctx, uint64_t alloc_words)
     if (e == hipSuccess)
         e = hipMemcpy(ctx->ref_planes_b, ctx->ref_planes + k, (alloc_words - k) * sizeof(uint2),
                       hipMemcpyDeviceToDevice);
+    const uint64_t line_words = ((words + gkd::LINE_WORDS - 1) / gkd::LINE_WORDS + 63) / 64 + 1;
+    if (e == hipSuccess)
+        e = hipMalloc(&ctx->ref_unk_lines, line_words * sizeof(unsigned long long));
+    if (e == hipSuccess)
+        e = hipMemset(ctx->ref_unk_lines, 0, line_words * sizeof(unsigned long long));
+    if (e == hipSuccess && unknown > 0)
+        e = gkd::launch_unknown_lines(ctx->ref_unk, words, ctx->ref_unk_lines, nullptr);
+    if (e == hipSuccess)
+        e = hipDeviceSynchronize();
     return e;
 }
 
@@ -182,7 +198,7 @@ int gk_load_reference(gk_ctx *ctx, const char *ascii, uint64_t len)
         e = hipMemcpy(&unknown, ctx->d_counter, sizeof unknown, hipMemcpyDeviceToHost);
     (void)hipFree(stage);
     if (e == hipSuccess)
-        e = make_shifted_planes(ctx, alloc_words);
+        e = finish_reference(ctx, words, alloc_words, unknown);
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference: pack");
     ctx->ref_len = len;
@@ -269,7 +285,7 @@ int gk_load_reference_2bit(gk_ctx *ctx, const uint32_t *packed, uint64_t len, ui
     if (e == hipSuccess)
         e = hipMemcpy(&unknown, ctx->d_counter, sizeof unknown, hipMemcpyDeviceToHost);
     if (e == hipSuccess)
-        e = make_shifted_planes(ctx, alloc_words);
+        e = finish_reference(ctx, words, alloc_words, unknown);
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: unpack");
     ctx->ref_len = len;
@@ -357,6 +373,7 @@ int prepare_batch(gk_ctx *ctx, const gk_batch *b, const char *who, gkd::FilterAr
     a.ref_planes = ctx->ref_planes;
     a.ref_planes_b = ctx->ref_planes_b;
     a.ref_unk = ctx->ref_unk;
+    a.ref_unk_lines = ctx->ref_unk_lines;
     a.ref_len = ctx->ref_len;
     a.ref_has_unknown = ctx->ref_unknown > 0;
     a.n_reads = b->n_reads;

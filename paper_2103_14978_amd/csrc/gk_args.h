@@ -28,12 +28,15 @@ constexpr uint32_t GK_PPL_RESIDENT = 65536;  // pairs-per-lane value meaning
 // 9 words that crosses a line of ref_planes lies within one line of
 // ref_planes_b, so every window of up to 256 bases costs one line fetch.
 constexpr uint32_t LINE_WORDS = 16;          // uint2 words per 128-byte line
+constexpr uint32_t LINE_BASES = 32 * LINE_WORDS;
 constexpr uint32_t REF_SHIFT_WORDS = 8;
 
 struct FilterArgs {
     const uint2 *ref_planes;
     const uint2 *ref_planes_b;  // ref_planes shifted by REF_SHIFT_WORDS, or NULL
     const uint32_t *ref_unk;
+    const unsigned long long *ref_unk_lines;  // bit L: bases [512 L, 512 L + 512)
+                                              // hold an unknown base
     uint64_t ref_len;
     uint32_t ref_has_unknown;
     uint32_t n_reads;

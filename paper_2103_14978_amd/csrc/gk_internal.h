@@ -47,6 +47,7 @@ struct gk_ctx {
     uint2 *ref_planes = nullptr;
     uint2 *ref_planes_b = nullptr;            // planes shifted by half a line
     uint32_t *ref_unk = nullptr;
+    unsigned long long *ref_unk_lines = nullptr;  // one bit per 512 bases
     unsigned long long *d_counter = nullptr;  // scratch for the unknown count
     uint32_t pairs_per_lane = 0;              // GK_OPT_PAIRS_PER_LANE
     int cu_count = 0;

@@ -338,6 +338,15 @@ __device__ __forceinline__ uint32_t pair_gate(const FilterArgs &a, const PairIdx
         return GK_INVALID;
     if ((uint64_t)p.pos + m > a.ref_len || (a.read_has_n && a.read_has_n[p.r]))
         return GK_UNDEFINED;
+    if (a.ref_has_unknown && a.ref_unk_lines) {
+        // Only windows touching a 512-base line that holds an unknown base
+        // read the unknown plane (m <= 512, so at most two lines).
+        const uint32_t l0 = p.pos / LINE_BASES, l1 = (p.pos + m - 1u) / LINE_BASES;
+        const bool near = ((a.ref_unk_lines[l0 >> 6] >> (l0 & 63u)) |
+                           (a.ref_unk_lines[l1 >> 6] >> (l1 & 63u))) & 1ull;
+        if (!near)
+            return PAIR_OK;
+    }
     if (a.ref_has_unknown) {
         const uint32_t s = p.pos & 31u;
         const uint32_t *u = a.ref_unk + (p.pos >> 5);

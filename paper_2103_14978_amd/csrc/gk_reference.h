@@ -20,4 +20,9 @@ hipError_t launch_mark_runs(const uint64_t *runs, uint64_t n_runs, uint32_t *unk
 hipError_t launch_count_unknown(const uint32_t *unk, uint64_t words, unsigned long long *counter,
                                 hipStream_t s);
 
+// lines[L / 64] bit L % 64 = 1 iff unknown-plane words [16 L, 16 L + 16) hold a
+// set bit; `lines` has ceil(ceil(words / 16) / 64) entries.
+hipError_t launch_unknown_lines(const uint32_t *unk, uint64_t words, unsigned long long *lines,
+                                hipStream_t s);
+
 }  // namespace gkd

@@ -63,7 +63,37 @@ __global__ __launch_bounds__(256) void k_count_unknown(const uint32_t *unk, uint
         atomicAdd(counter, (unsigned long long)c);
 }
 
+// One lane per 512-base line of the reference; a wave's 64 answers make one
+// 64-bit word of the summary.
+__global__ __launch_bounds__(256) void k_unknown_lines(const uint32_t *unk, uint64_t words,
+                                                       unsigned long long *lines)
+{
+    const uint64_t line = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+    const uint64_t nlines = (words + LINE_WORDS - 1) / LINE_WORDS;
+    uint32_t any = 0;
+    if (line < nlines) {
+        const uint64_t w0 = line * LINE_WORDS;
+        const uint64_t w1 = w0 + LINE_WORDS < words ? w0 + LINE_WORDS : words;
+        for (uint64_t w = w0; w < w1; ++w)
+            any |= unk[w];
+    }
+    const unsigned long long bits = __ballot(any != 0u);
+    if ((threadIdx.x & 63u) == 0u && line < nlines)
+        lines[line / 64] = bits;
+}
+
 }  // namespace
+
+hipError_t launch_unknown_lines(const uint32_t *unk, uint64_t words, unsigned long long *lines,
+                                hipStream_t s)
+{
+    const uint64_t nlines = (words + LINE_WORDS - 1) / LINE_WORDS;
+    if (nlines == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_unknown_lines, dim3((uint32_t)((nlines + 255) / 256)), dim3(256), 0, s,
+                       unk, words, lines);
+    return hipGetLastError();
+}
 
 hipError_t launch_unpack_reference(const uint32_t *packed, uint64_t first, uint64_t n,
                                    uint32_t layout, uint2 *planes, hipStream_t s)

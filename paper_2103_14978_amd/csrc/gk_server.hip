@@ -208,6 +208,7 @@ gkd::FilterArgs args_for(const gk_server *s, const Req *q)
     a.ref_planes = c->ref_planes;
     a.ref_planes_b = c->ref_planes_b;
     a.ref_unk = c->ref_unk;
+    a.ref_unk_lines = c->ref_unk_lines;
     a.ref_len = c->ref_len;
     a.ref_has_unknown = c->ref_unknown > 0;
     a.n_reads = q->r.n_reads;
