@@ -76,6 +76,20 @@ def traffic_from_profile(kernel_hash: str, n_pairs: int,
     return d.get("hbm_bytes_per_launch")
 
 
+def host_cpu_model() -> str:
+    """The host's CPU model and logical CPU count, for the CPU baseline."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs visible"
+
+
 def plain_kernel_name(words: int, e: int, pairs_per_lane: int) -> str:
     """The plain launch's kernel for this shape: the library takes one pair per
     lane when (2e+1)*W < 60 under the automatic setting (0)."""
@@ -352,13 +366,14 @@ def main() -> int:
                "sample": f"first {sample} pairs of the same batch, {threads} threads, "
                          f"{dt:.1f}s wall"}
         log(f"cpu baseline {sample / dt:.0f} pairs/s on {threads} threads")
-        one = min(n_pairs, 1 << 16)
+        one = min(n_pairs, 1 << 18)
         t = time.perf_counter()
         oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read[:one], ps.cand_pos[:one], e,
                             n_threads=1)
         dt1 = time.perf_counter() - t
         cpu["one_core"] = {"value": round(one / dt1, 1), "unit": "pairs/s",
                            "sample": f"first {one} pairs, 1 thread, {dt1:.2f}s wall"}
+        cpu["host_cpu"] = host_cpu_model()
 
     out = {
         "metric": "filtered pairs/sec (100bp, e=5) on 1 MI355X, bit-exact",
