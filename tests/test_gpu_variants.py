@@ -34,7 +34,8 @@ def test_variants_plain_and_mixed(gkctx, mixed_case, flags):
     r0, _ = oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read, ps.cand_pos, ps.e,
                                 n_threads=gen.default_threads())
     assert not np.array_equal(ra, r0)          # the variant changes some decisions
-    dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=300)
+    layout = gk.GK_READS_INTERLEAVED if flags == FLAGS[-1] else gk.GK_READS_SPLIT
+    dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=300, layout=layout)
     for mixed in (False, True):
         dp = device.upload_pairs(ps.pair_read, ps.cand_pos, ps.e)
         b = device.batch_for(dr, dp, max_read_len=300, flags=flags)

@@ -49,8 +49,8 @@ def edited_pairs(rng, ref, n, max_len=300, max_e=31, min_len=1):
     return reads, off, np.arange(n, dtype=np.uint32), np.array(pos, np.uint32), e
 
 
-def verify(ctx, reads, off, pr, pos, e, max_len, accept=None):
-    dr = device.encode_reads(ctx, reads, off, max_len=max_len)
+def verify(ctx, reads, off, pr, pos, e, max_len, accept=None, layout=0):
+    dr = device.encode_reads(ctx, reads, off, max_len=max_len, layout=layout)
     dp = device.upload_pairs(pr, pos, e)
     b = device.batch_for(dr, dp, max_read_len=max_len)
     dist = torch.empty(len(pos), dtype=torch.int16, device="cuda")
@@ -157,3 +157,15 @@ def test_verify_errors(gkctx):
     gk.gk_verify(gkctx, b, None, dist, None)
     torch.cuda.synchronize()
     assert int(dist.cpu().numpy().view(np.uint16)[0]) == 0
+
+
+def test_verify_interleaved_layout(gkctx):
+    """The interleaved read layout gives the same distances."""
+    rng = np.random.default_rng(91)
+    ref = gen.c0_reference()
+    gk.gk_load_reference(gkctx, ref)
+    reads, off, pr, pos, e = edited_pairs(rng, ref, 3000, max_len=250)
+    say("case: verify interleaved layout")
+    d1 = verify(gkctx, reads, off, pr, pos, e, 250, layout=gk.GK_READS_INTERLEAVED)
+    want = oracle_dist(ref, reads, off, pr, pos, e)
+    assert np.array_equal(d1, want)
