@@ -224,6 +224,16 @@ int gk_filter(gk_ctx *ctx, const gk_batch *batch, void *stream);
  * while the batch is in flight: the outputs are then unspecified),
  * n_reads >= 2^30, or max_read_len outside 1..GK_MAX_READ_LEN; GK_ENOREF
  * without a reference; GK_ENOMEM when the device buffers do not fit.
+ *
+ * Host-encoded reads (the paper's host-encoded mode, Sec. 3.3): when packed
+ * is not NULL, ascii and read_off are ignored and the reads come already
+ * 2-bit encoded: read r's rows = ceil(max_read_len / 16) words are
+ * packed[r * rows .. r * rows + rows), 16 bases per word in packed_layout
+ * (GK_READS_SPLIT or GK_READS_INTERLEAVED, as gk_encode_reads writes them),
+ * with every code bit at or beyond read_len[r] equal to 0.  read_len (HOST,
+ * n_reads) is then required, read_has_n (HOST, n_reads, 1 = the read holds an
+ * unknown base) is optional.  The GPU transposes the rows into the filter's
+ * layout; about a quarter of the ASCII bytes cross PCIe.
  */
 typedef struct gk_host_batch {
     uint32_t        n_reads;
@@ -239,6 +249,10 @@ typedef struct gk_host_batch {
     uint8_t        *accept;        /* HOST out, n_pairs                      */
     uint16_t       *est;           /* HOST out, n_pairs                      */
     uint32_t        flags;         /* GK_FLAG_*, as gk_batch.flags           */
+    const uint32_t *packed;        /* HOST host-encoded reads, or NULL       */
+    const uint16_t *read_len;      /* HOST n_reads (with packed)             */
+    const uint8_t  *read_has_n;    /* HOST n_reads or NULL (with packed)     */
+    uint32_t        packed_layout; /* GK_READS_* of packed                   */
 } gk_host_batch;
 
 int gk_filter_host(gk_ctx *ctx, const gk_host_batch *batch);

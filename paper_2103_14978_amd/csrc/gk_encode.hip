@@ -126,7 +126,31 @@ __global__ __launch_bounds__(256) void k_pack_reference(const uint8_t *ascii, ui
         atomicAdd(counter, (unsigned long long)c);
 }
 
+// One lane per read: its rows consecutive words in, one word per transposed
+// row out (the writes of a wave to one row are consecutive).
+__global__ __launch_bounds__(256) void k_transpose_reads(const uint32_t *rowmajor,
+                                                         uint32_t n_reads, uint32_t rows,
+                                                         uint32_t pitch, uint32_t *out)
+{
+    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+    if (r >= n_reads)
+        return;
+    const uint32_t *src = rowmajor + (size_t)r * rows;
+    for (uint32_t w = 0; w < rows; ++w)
+        out[(size_t)w * pitch + r] = src[w];
+}
+
 }  // namespace
+
+hipError_t launch_transpose_reads(const uint32_t *rowmajor, uint32_t n_reads, uint32_t rows,
+                                  uint32_t pitch, uint32_t *out, hipStream_t s)
+{
+    if (n_reads == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_transpose_reads, dim3((n_reads + 255) / 256), dim3(256), 0, s, rowmajor,
+                       n_reads, rows, pitch, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_encode_reads(const uint8_t *ascii, const uint64_t *read_off, uint32_t n_reads,
                                uint32_t pitch, uint32_t rows, uint32_t layout, uint32_t *packed,

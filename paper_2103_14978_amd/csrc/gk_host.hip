@@ -149,18 +149,28 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         return fail(ctx, GK_EINVAL, "gk_filter_host: NULL pair or output buffer");
     if (!b->pair_read && b->n_pairs != b->n_reads)
         return fail(ctx, GK_EINVAL, "gk_filter_host: pair_read NULL needs n_pairs == n_reads");
-    if (b->n_reads > 0 && (!b->ascii || !b->read_off))
-        return fail(ctx, GK_EINVAL, "gk_filter_host: NULL read buffer");
-    if (b->n_reads > 0 && b->read_off[0] != 0)
-        return fail(ctx, GK_EINVAL, "gk_filter_host: read_off[0] must be 0");
+    const bool host_encoded = b->packed != nullptr;
+    if (host_encoded) {
+        if (b->n_reads > 0 && !b->read_len)
+            return fail(ctx, GK_EINVAL, "gk_filter_host: packed reads need read_len");
+        if (b->packed_layout != GK_READS_SPLIT && b->packed_layout != GK_READS_INTERLEAVED)
+            return fail(ctx, GK_EINVAL, "gk_filter_host: unknown packed_layout");
+    } else {
+        if (b->n_reads > 0 && (!b->ascii || !b->read_off))
+            return fail(ctx, GK_EINVAL, "gk_filter_host: NULL read buffer");
+        if (b->n_reads > 0 && b->read_off[0] != 0)
+            return fail(ctx, GK_EINVAL, "gk_filter_host: read_off[0] must be 0");
+    }
     DeviceScope g(ctx->device);
     if (!g.ok)
         return fail(ctx, GK_EDEVICE, "gk_filter_host: hipSetDevice failed");
 
     const uint64_t nr = b->n_reads, np = b->n_pairs;
-    const uint64_t bytes = nr ? b->read_off[nr] : 0;
     const uint32_t pitch = (uint32_t)std::max<uint64_t>(64, (nr + 63) / 64 * 64);
     const uint32_t rows = (b->max_read_len + 15) / 16;
+    // ASCII text, or the host-encoded rows staged in the same buffer.
+    const uint64_t bytes = host_encoded ? nr * rows * sizeof(uint32_t)
+                                        : (nr ? b->read_off[nr] : 0);
     const bool identity = b->pair_read == nullptr;
 
     // Chunks of at least 2^20 pairs, at most 16 of them.
@@ -180,7 +190,21 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         // Read chunk j: offsets must be non-decreasing and within the text.
         const uint64_t r0 = std::min<uint64_t>(nr, (uint64_t)j * R);
         const uint64_t r1 = std::min<uint64_t>(nr, r0 + R);
-        if (r1 > r0) {
+        uint32_t *rows_dev =
+            host_encoded ? reinterpret_cast<uint32_t *>(h.ascii) + r0 * rows : nullptr;
+        if (r1 > r0 && host_encoded) {
+            e = hipMemcpyAsync(rows_dev, b->packed + r0 * rows,
+                               (r1 - r0) * rows * sizeof(uint32_t), hipMemcpyHostToDevice,
+                               h.s_in);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(h.len + r0, b->read_len + r0, (r1 - r0) * sizeof(uint16_t),
+                                   hipMemcpyHostToDevice, h.s_in);
+            if (e == hipSuccess)
+                e = b->read_has_n
+                        ? hipMemcpyAsync(h.has_n + r0, b->read_has_n + r0, r1 - r0,
+                                         hipMemcpyHostToDevice, h.s_in)
+                        : hipMemsetAsync(h.has_n + r0, 0, r1 - r0, h.s_in);
+        } else if (r1 > r0) {
             for (uint64_t r = r0; r < r1 && !bad_offsets; ++r)
                 bad_offsets = b->read_off[r + 1] < b->read_off[r];
             bad_offsets = bad_offsets || b->read_off[r1] > bytes;
@@ -222,9 +246,12 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         if (e == hipSuccess)
             e = hipStreamWaitEvent(h.s_comp, h.ev_in[j], 0);
         if (e == hipSuccess && r1 > r0)
-            e = gkd::launch_encode_reads(h.ascii, h.off + r0, (uint32_t)(r1 - r0), pitch, rows,
-                                         GK_READS_SPLIT, h.packed + r0, h.len + r0,
-                                         h.has_n + r0, h.s_comp);
+            e = host_encoded
+                    ? gkd::launch_transpose_reads(rows_dev, (uint32_t)(r1 - r0), rows, pitch,
+                                                  h.packed + r0, h.s_comp)
+                    : gkd::launch_encode_reads(h.ascii, h.off + r0, (uint32_t)(r1 - r0), pitch,
+                                               rows, GK_READS_SPLIT, h.packed + r0, h.len + r0,
+                                               h.has_n + r0, h.s_comp);
         // Filter every pair chunk whose reads are now encoded, in order.
         while (e == hipSuccess && next_q <= j && need[next_q] <= j) {
             const uint32_t q = next_q++;
@@ -236,7 +263,7 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
             fb.pitch = pitch;
             fb.max_read_len = b->max_read_len;
             fb.e_uniform = b->e_uniform;
-            fb.read_layout = GK_READS_SPLIT;
+            fb.read_layout = host_encoded ? b->packed_layout : GK_READS_SPLIT;
             fb.flags = b->flags;
             fb.n_pairs = q1 - q0;
             fb.cand_pos = h.cand_pos + q0;

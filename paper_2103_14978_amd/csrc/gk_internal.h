@@ -22,7 +22,7 @@ struct MixedConfig {
 struct HostPipe {
     hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
     uint8_t *ascii = nullptr;
-    uint64_t ascii_cap = 0;      // bytes
+    uint64_t ascii_cap = 0;      // bytes (or host-encoded row-major words)
     uint64_t *off = nullptr;
     uint32_t *packed = nullptr;
     uint16_t *len = nullptr;
@@ -115,6 +115,11 @@ hipError_t launch_filter(const FilterArgs &a, uint32_t words, uint32_t layout,
 hipError_t launch_encode_reads(const uint8_t *ascii, const uint64_t *read_off, uint32_t n_reads,
                                uint32_t pitch, uint32_t rows, uint32_t layout, uint32_t *packed,
                                uint16_t *len_out, uint8_t *has_n_out, hipStream_t s);
+
+// Host-encoded reads, rows words per read in read order, to the transposed
+// layout: out[w * pitch + r] = rowmajor[r * rows + w] for r < n_reads.
+hipError_t launch_transpose_reads(const uint32_t *rowmajor, uint32_t n_reads, uint32_t rows,
+                                  uint32_t pitch, uint32_t *out, hipStream_t s);
 
 // Pack bases [first, first + n) of the reference, first a multiple of 32,
 // from the device staging buffer `ascii` (holding those n bytes) into the

@@ -77,6 +77,10 @@ class gk_host_batch(ctypes.Structure):
         ("accept", ctypes.c_void_p),
         ("est", ctypes.c_void_p),
         ("flags", ctypes.c_uint32),
+        ("packed", ctypes.c_void_p),
+        ("read_len", ctypes.c_void_p),
+        ("read_has_n", ctypes.c_void_p),
+        ("packed_layout", ctypes.c_uint32),
     ]
 
 
@@ -306,19 +310,23 @@ def host_ptr(x):
 
 def gk_filter_host(ctx, ascii, read_off, cand_pos, accept, est, *, max_read_len: int,
                    pair_read=None, e=None, e_uniform: int = 0, n_reads=None,
-                   n_pairs=None, flags: int = 0) -> None:
+                   n_pairs=None, flags: int = 0, packed=None, read_len=None, read_has_n=None,
+                   packed_layout: int = GK_READS_SPLIT) -> None:
     """Host buffers in, host results out (synchronous).  Arrays are
     contiguous numpy arrays of the ABI's dtypes, or CPU torch tensors (e.g.
-    pinned byte buffers) with n_reads and n_pairs given."""
+    pinned byte buffers) with n_reads and n_pairs given.  With packed (host-
+    encoded rows) and read_len, ascii and read_off are not used (may be None)."""
     if n_reads is None:
-        n_reads = len(read_off) - 1
+        n_reads = len(read_len) if packed is not None else len(read_off) - 1
     if n_pairs is None:
         n_pairs = len(cand_pos)
     b = gk_host_batch(n_reads=n_reads, max_read_len=max_read_len, ascii=host_ptr(ascii),
                       read_off=host_ptr(read_off), n_pairs=n_pairs,
                       pair_read=host_ptr(pair_read), cand_pos=host_ptr(cand_pos),
                       e=host_ptr(e), e_uniform=e_uniform, accept=host_ptr(accept),
-                      est=host_ptr(est), flags=flags)
+                      est=host_ptr(est), flags=flags, packed=host_ptr(packed),
+                      read_len=host_ptr(read_len), read_has_n=host_ptr(read_has_n),
+                      packed_layout=packed_layout)
     _check(ctx, lib().gk_filter_host(ctx, ctypes.byref(b)), "gk_filter_host")
 
 

@@ -140,3 +140,27 @@ def unknown_runs(ascii):
     starts = np.nonzero(d == 1)[0]
     ends = np.nonzero(d == -1)[0]
     return np.stack([starts, ends - starts], 1).astype(np.uint64)
+
+
+def pack_reads_rows(reads, read_off, rows, layout):
+    """Host encoding of reads for gk_filter_host's packed input: rows words
+    per read, 16 bases per word in `layout`, code bits past each read's end
+    zero; returns (packed uint32 [n_reads * rows], read_len uint16, has_n
+    uint8).  Unknown bases get code 0 and set has_n."""
+    reads = np.asarray(reads, np.uint8)
+    off = np.asarray(read_off, np.int64)
+    n = len(off) - 1
+    lens = np.minimum(np.diff(off), 16 * rows)
+    j = np.arange(16 * rows)
+    valid = j[None, :] < lens[:, None]
+    idx = np.where(valid, off[:-1, None] + j[None, :], 0)
+    ch = np.where(valid, reads[idx], ord("A"))
+    codes = np.where(valid, _CODE[ch], 0).astype(np.uint32).reshape(n, rows, 16)
+    has_n = (valid & ~BASE_MASK[ch]).any(axis=1).astype(np.uint8)
+    k = np.arange(16, dtype=np.uint32)
+    if layout == gk.GK_READS_SPLIT:
+        words = ((codes & 1) << k).sum(2) | ((codes >> 1) << (16 + k)).sum(2)
+    else:
+        words = (codes << (2 * k)).sum(2)
+    return (np.ascontiguousarray(words.astype(np.uint32).reshape(-1)),
+            np.diff(off).astype(np.uint16), has_n)

@@ -13,7 +13,8 @@ STRUCTS = {
                  "read_len", "read_has_n", "n_pairs", "pair_read", "cand_pos", "e", "accept",
                  "est", "accept_bits", "flags"],
     "gk_host_batch": ["n_reads", "max_read_len", "ascii", "read_off", "n_pairs", "pair_read",
-                      "cand_pos", "e", "e_uniform", "accept", "est", "flags"],
+                      "cand_pos", "e", "e_uniform", "accept", "est", "flags", "packed",
+                      "read_len", "read_has_n", "packed_layout"],
     "gk_request": ["reads", "read_off", "n_reads", "e", "pair_read", "cand_pos", "n_pairs",
                    "accept", "est", "t_arrival_us"],
     "gk_request_stats": ["status", "n_pairs", "t_submit_us", "t_admit_us", "t_done_us"],

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import gen
-from gpu_cases import assert_same, concat_reads, run_gpu, run_oracle, say
+from gpu_cases import assert_same, concat_reads, pack_reads_rows, run_gpu, run_oracle, say
 
 pytestmark = pytest.mark.gpu
 
@@ -137,3 +137,39 @@ def test_host_status_and_errors(gkctx):
     # The context still works after the errors.
     a, s = host_filter(gkctx, ps, max_read_len=128, e_uniform=3)
     assert a[0] == gk.GK_ACCEPT
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_host_encoded_reads(gkctx, layout):
+    """Host-encoded reads (packed rows + lengths + unknown flags) give the same
+    results as ASCII reads; reads of several lengths, some with unknown bases,
+    several candidates per read, more than one chunk."""
+    from paper_2103_14978_amd import gk
+    ref = gen.c1_reference()
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c2_pairs(ref, 150, 7, n_pairs=(1 << 21) + 77)
+    reads = ps.reads.copy()
+    reads[np.arange(500, len(reads), 7919)] = ord("N")
+    rows = (150 + 15) // 16
+    packed, lens, has_n = pack_reads_rows(reads, ps.read_off, rows, layout)
+    assert has_n.sum() > 0
+    say(f"case: host-encoded reads layout={layout} pairs={ps.n_pairs}")
+    acc = np.zeros(ps.n_pairs, np.uint8)
+    est = np.zeros(ps.n_pairs, np.uint16)
+    gk.gk_filter_host(gkctx, None, None, ps.cand_pos, acc, est, max_read_len=150,
+                      pair_read=ps.pair_read, e_uniform=7, packed=packed, read_len=lens,
+                      read_has_n=has_n, packed_layout=layout)
+    acc2 = np.zeros(ps.n_pairs, np.uint8)
+    est2 = np.zeros(ps.n_pairs, np.uint16)
+    gk.gk_filter_host(gkctx, reads, ps.read_off, ps.cand_pos, acc2, est2, max_read_len=150,
+                      pair_read=ps.pair_read, e_uniform=7)
+    assert_same(acc, est, acc2, est2, f"host-encoded vs ascii layout={layout}")
+    assert np.any(acc == gk.GK_UNDEFINED)
+    idx = np.arange(0, ps.n_pairs, 61)
+    ra, rs = run_oracle(ref, reads, ps.read_off, ps.pair_read[idx], ps.cand_pos[idx], 7)
+    assert_same(acc[idx], est[idx], ra, rs, "host-encoded vs oracle")
+    with pytest.raises(gk.GkError) as ei:
+        gk.gk_filter_host(gkctx, None, None, ps.cand_pos, acc, est, max_read_len=150,
+                          pair_read=ps.pair_read, e_uniform=7, packed=packed, read_len=None,
+                          n_reads=len(lens))
+    assert ei.value.status == gk.GK_EINVAL
