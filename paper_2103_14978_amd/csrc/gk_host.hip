@@ -141,6 +141,8 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         return fail(ctx, GK_EINVAL, "gk_filter_host: e_uniform must be 0..255");
     if (b->n_reads >= (1u << 30))
         return fail(ctx, GK_EINVAL, "gk_filter_host: n_reads must be below 2^30");
+    if (b->flags & ~(GK_FLAG_NO_REFINE | GK_FLAG_HAMMING_FASTPATH))
+        return fail(ctx, GK_EINVAL, "gk_filter_host: unknown flags");
     if (b->n_pairs == 0)
         return GK_OK;
     if (b->n_pairs >= (1ull << 38))
