@@ -75,3 +75,59 @@ def test_unknown_flags_rejected(gkctx):
     with pytest.raises(gk.GkError) as ei:
         gk.gk_filter(gkctx, device.batch_for(dr, dp, e_uniform=2, flags=4), None)
     assert ei.value.status == gk.GK_EINVAL
+
+
+
+def _large_e_case(seed):
+    """Pairs with e in 30..90 that the filter does not accept wholesale.
+
+    At such thresholds almost every window passes, so the windows are cut from
+    a planted stretch of A/C bases and each read carries a block of G/T bases
+    of length e..3e+8 (at the start, the end or inside).  Block bases mismatch
+    the window under every shift; the AND keeps about (block - 2e) of them, more
+    at a read end, where the vacated positions (compared with 'A') decide
+    whether refinement matters.  This splits decisions near e."""
+    from gpu_cases import concat_reads
+    rng = np.random.default_rng(seed)
+    ref = gen.reference(400_000, 0.41, 4244)
+    lo, hi = 200_000, 212_000
+    ref[lo:hi] = np.frombuffer(b"AC", np.uint8)[rng.integers(0, 2, hi - lo)]
+    seqs, pos, es = [], [], []
+    for m in (100, 128, 161, 256, 300):
+        for i in range(300):
+            e = int(rng.integers(30, min(90, (m - 4) // 3) + 1))
+            p = int(rng.integers(lo, hi - m))
+            s = ref[p:p + m].copy()
+            k = int(rng.integers(e, min(m, 3 * e + 8) + 1))
+            at = (0, m - k, int(rng.integers(0, m - k + 1)))[i % 3]
+            s[at:at + k] = np.frombuffer(b"GT", np.uint8)[rng.integers(0, 2, k)]
+            seqs.append(s.tobytes())
+            pos.append(p + int(rng.integers(-2, 3)) * (i % 4 == 0))
+            es.append(e)
+    reads, off = concat_reads(seqs)
+    return (ref, reads, off, np.arange(len(seqs), dtype=np.uint32),
+            np.array(pos, np.uint32), np.array(es, np.uint8))
+
+
+@pytest.mark.parametrize("flags", [0] + FLAGS)
+def test_variants_large_e_general_path(gkctx, flags):
+    """Thresholds of 30..90 (whole-word shifts of the general path, and the
+    mixed launch's residual pass), by default and under each variant."""
+    ref, reads, off, pr, pos, e = _large_e_case(300 + flags)
+    gk.gk_load_reference(gkctx, ref)
+    say(f"case: variants large e flags={flags} pairs={len(pr)}")
+    ra, rs = oracle.filter_batch(reads, off, ref, pr, pos, e, flags=flags,
+                                 n_threads=gen.default_threads())
+    r0, _ = oracle.filter_batch(reads, off, ref, pr, pos, e,
+                                n_threads=gen.default_threads())
+    assert 0.2 < np.mean(ra == gk.GK_ACCEPT) < 0.8
+    if flags & gk.GK_FLAG_NO_REFINE:
+        assert not np.array_equal(ra, r0)
+    dr = device.encode_reads(gkctx, reads, off, max_len=300)
+    for mixed in (False, True):
+        dp = device.upload_pairs(pr, pos, e)
+        b = device.batch_for(dr, dp, max_read_len=300, flags=flags)
+        (gk.gk_filter_mixed if mixed else gk.gk_filter)(gkctx, b, None)
+        torch.cuda.synchronize()
+        a, s = device.results(dp)
+        assert_same(a, s, ra, rs, f"large e flags={flags} mixed={mixed}")
