@@ -145,11 +145,14 @@ def main() -> int:
                     help="run one plain 256 MiB device copy kernel first (counter calibration)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target wall time of the CPU-baseline sample")
-    ap.add_argument("--workload", choices=["plain", "mixed", "served"], default="plain",
+    ap.add_argument("--workload", choices=["plain", "mixed", "served", "sweep"],
+                    default="plain",
                     help="plain: 100 bp, e=5 (the headline); mixed: 2^26 pairs of mixed "
                          "lengths and per-pair e, persistent launch vs one launch per "
                          "(length, e) group; served: Poisson request stream over a 3.1 Gbp "
-                         "reference, batched server vs sequential per-request launches")
+                         "reference, batched server vs sequential per-request launches; "
+                         "sweep: the plain launch at 100 bp for e = 0..10 and at 150 / 250 bp "
+                         "for e = 2, 5, 10 %% of the length")
     ap.add_argument("--lambdas",
                     default="50,100,200,500,1000,2000,3000,3500,4000,4500,5000,6000,8000",
                     help="served: arrival rates (requests/s)")
@@ -194,6 +197,8 @@ def main() -> int:
         return bench_mixed(args, log)
     if args.workload == "served":
         return bench_served(args, log)
+    if args.workload == "sweep":
+        return bench_sweep(args, log)
 
     t = time.time()
     ref = gen.c1_reference()
@@ -451,6 +456,106 @@ def main() -> int:
         "filter_time": ft,
         "verification": verify,
         "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+    gk.gk_destroy(ctx)
+    return 0
+
+
+def sweep_bytes_per_pair(m: int, cands_per_read: float) -> float:
+    """Algorithmic bytes per pair when a read serves cands_per_read pairs: the
+    window (m/4 B), the packed read and its length shared by its candidates,
+    read index + position (8 B), accept + est (3 B)."""
+    return m / 4 + (m / 4 + 2) / cands_per_read + 8 + 3
+
+
+def bench_sweep(args, log) -> int:
+    """The plain launch across thresholds and read lengths (the paper's Sec. 5
+    sweeps of e and m): 2^24 pairs of 100 bp for each e in 0..10, and 2^25
+    pairs at 150 bp (e = 3, 7, 15) and 250 bp (e = 5, 12, 25) with several
+    candidates per read.  Per point: kernel time from HIP events on the launch
+    stream, the VALU-roof fraction of the algorithmic op count, the
+    algorithmic HBM rate, and a sampled bit-exact check against the oracle."""
+    import torch
+    import gen
+    import oracle
+    from paper_2103_14978_amd import device, gk
+
+    ref = gen.c1_reference()
+    ctx = gk.gk_create(0)
+    gk.gk_load_reference(ctx, ref)
+    stream = torch.cuda.current_stream()
+    steps = max(3, min(args.steps, 20))
+    points = [(100, e) for e in range(11)] + [(150, 3), (150, 7), (150, 15),
+                                              (250, 5), (250, 12), (250, 25)]
+    rows, headline = [], None
+    for m, e in points:
+        t = time.time()
+        ps = gen.c1_pairs(ref, e) if m == 100 else gen.c2_pairs(ref, m, e)
+        n = ps.n_pairs
+        identity = bool(ps.n_reads == n and
+                        np.array_equal(ps.pair_read, np.arange(n, dtype=np.uint32)))
+        dr = device.encode_reads(ctx, ps.reads, ps.read_off, max_len=m)
+        dp = device.upload_pairs(None if identity else ps.pair_read, ps.cand_pos, None)
+        batch = device.batch_for(dr, dp, e_uniform=e, max_read_len=m)
+        for _ in range(3):
+            gk.gk_filter(ctx, batch, stream)
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+        t0 = time.perf_counter()
+        for a0, a1 in ev:
+            a0.record(stream)
+            gk.gk_filter(ctx, batch, stream)
+            a1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = [a0.elapsed_time(a1) for a0, a1 in ev]
+        k_s = float(np.mean(kms)) / 1e3
+        a_gpu, s_gpu = device.results(dp)
+        rng = np.random.default_rng(4321 + m + e)
+        idx = np.sort(rng.choice(n, size=min(n, 1 << 13), replace=False))
+        ra, rs = oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read[idx],
+                                     ps.cand_pos[idx], e, n_threads=gen.default_threads())
+        mism = int(np.sum((a_gpu[idx] != ra) | (s_gpu[idx] != rs)))
+        words = (m + 31) // 32
+        cpr = n / ps.n_reads
+        tops = ops_per_pair(m, e) * n / k_s / 1e12
+        row = {"read_len": m, "e": e, "pairs": int(n), "reads": int(ps.n_reads),
+               "kernel": plain_kernel_name(words, e, 0) + ">",
+               "kernel_ms": round(k_s * 1e3, 4), "kernel_ms_min": round(min(kms), 4),
+               "kernel_ms_median": round(float(np.median(kms)), 4),
+               "kernel_pairs_per_s": round(n / k_s, 1), "wall_pairs_per_s": round(n * steps / wall, 1),
+               "ops_per_pair": ops_per_pair(m, e),
+               "valu_frac": round(tops / VALU_PEAK_TOPS, 4),
+               "alg_bytes_per_pair": round(sweep_bytes_per_pair(m, cpr), 2),
+               "hbm_alg_GBs": round(sweep_bytes_per_pair(m, cpr) * n / k_s / 1e9, 1),
+               "accepted_frac": round(float(np.mean(a_gpu == gk.GK_ACCEPT)), 4),
+               "sampled_pairs": int(len(idx)), "mismatches": mism}
+        rows.append(row)
+        if (m, e) == (100, 5):
+            headline = (row, steps, wall)
+        log(f"{m} bp e={e}: {k_s * 1e3:.4f} ms, {n / k_s / 1e9:.2f} G pairs/s, "
+            f"VALU {row['valu_frac']:.3f}, {mism} mismatches of {len(idx)} "
+            f"({time.time() - t:.1f}s)")
+        del batch, dp, dr, ps
+        torch.cuda.empty_cache()
+    row, hsteps, hwall = headline
+    out = {
+        "metric": "filtered pairs/sec (100bp, e=5) on 1 MI355X, bit-exact",
+        "value": row["wall_pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": hsteps,
+        "warmup": 3, "ms_per_step": round(hwall * 1e3 / hsteps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "plain filter sweep: 2^24 pairs of 100 bp for e = 0..10, "
+                               "2^25 pairs at 150 bp (e = 3, 7, 15) and 250 bp (e = 5, 12, 25), "
+                               "100 Mbp GC-41% reference"},
+        "roofline": {"bound": "alu", "kernel": row["kernel"],
+                     "achieved": round(row["valu_frac"] * VALU_PEAK_TOPS, 3),
+                     "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
+                     "frac": row["valu_frac"], "traffic": None},
+        "cpu_baseline": None,
+        "sweep": rows,
     }
     print(json.dumps(out), flush=True)
     gk.gk_destroy(ctx)
