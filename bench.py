@@ -116,10 +116,10 @@ def host_cpu_model() -> str:
 
 
 def plain_kernel_name(words: int, e: int, pairs_per_lane: int) -> str:
-    """The plain launch's kernel for this shape: the library takes one pair per
-    lane when (2e+1)*W < 60 under the automatic setting (0)."""
+    """The plain launch's kernel for this shape: the automatic setting (0)
+    takes one pair per lane."""
     if pairs_per_lane == 0:
-        pairs_per_lane = 4 if (2 * e + 1) * words >= 60 else 1
+        pairs_per_lane = 1
     return f"k_filter_single<{words}" if pairs_per_lane == 1 else f"k_filter<{words}"
 
 
@@ -475,7 +475,9 @@ def bench_sweep(args, log) -> int:
     pairs at 150 bp (e = 3, 7, 15) and 250 bp (e = 5, 12, 25) with several
     candidates per read.  Per point: kernel time from HIP events on the launch
     stream, the VALU-roof fraction of the algorithmic op count, the
-    algorithmic HBM rate, and a sampled bit-exact check against the oracle."""
+    algorithmic HBM rate, a sampled bit-exact check against the oracle, and
+    the time to verify the accepted pairs (gk_verify) with sampled distances
+    checked against the oracle's."""
     import torch
     import gen
     import oracle
@@ -483,6 +485,7 @@ def bench_sweep(args, log) -> int:
 
     ref = gen.c1_reference()
     ctx = gk.gk_create(0)
+    gk.gk_set_option(ctx, gk.GK_OPT_PAIRS_PER_LANE, args.pairs_per_lane)
     gk.gk_load_reference(ctx, ref)
     stream = torch.cuda.current_stream()
     steps = max(3, min(args.steps, 20))
@@ -518,11 +521,31 @@ def bench_sweep(args, log) -> int:
         ra, rs = oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read[idx],
                                      ps.cand_pos[idx], e, n_threads=gen.default_threads())
         mism = int(np.sum((a_gpu[idx] != ra) | (s_gpu[idx] != rs)))
+        # Verification of this point's accepted pairs (gk_verify after the
+        # filter), with sampled distances against the oracle's.
+        dist = torch.empty(n, dtype=torch.int16, device="cuda")
+        gk.gk_verify(ctx, batch, dp.accept, dist, stream)
+        torch.cuda.synchronize()
+        vev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(5)]
+        for a0, a1 in vev:
+            a0.record(stream)
+            gk.gk_verify(ctx, batch, dp.accept, dist, stream)
+            a1.record(stream)
+        torch.cuda.synchronize()
+        v_ms = float(np.mean([a0.elapsed_time(a1) for a0, a1 in vev]))
+        d_gpu = dist.cpu().numpy().view(np.uint16)
+        acc_idx = np.nonzero(a_gpu == gk.GK_ACCEPT)[0]
+        vidx = np.sort(rng.choice(acc_idx, size=min(len(acc_idx), 1 << 11), replace=False))
+        want = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[vidx],
+                                        ps.cand_pos[vidx], e, n_threads=gen.default_threads())
+        vmism = int(np.sum(d_gpu[vidx] != want))
+        del dist
         words = (m + 31) // 32
         cpr = n / ps.n_reads
         tops = ops_per_pair(m, e) * n / k_s / 1e12
         row = {"read_len": m, "e": e, "pairs": int(n), "reads": int(ps.n_reads),
-               "kernel": plain_kernel_name(words, e, 0) + ">",
+               "kernel": plain_kernel_name(words, e, args.pairs_per_lane) + ">",
                "kernel_ms": round(k_s * 1e3, 4), "kernel_ms_min": round(min(kms), 4),
                "kernel_ms_median": round(float(np.median(kms)), 4),
                "kernel_pairs_per_s": round(n / k_s, 1), "wall_pairs_per_s": round(n * steps / wall, 1),
@@ -531,12 +554,16 @@ def bench_sweep(args, log) -> int:
                "alg_bytes_per_pair": round(sweep_bytes_per_pair(m, cpr), 2),
                "hbm_alg_GBs": round(sweep_bytes_per_pair(m, cpr) * n / k_s / 1e9, 1),
                "accepted_frac": round(float(np.mean(a_gpu == gk.GK_ACCEPT)), 4),
-               "sampled_pairs": int(len(idx)), "mismatches": mism}
+               "sampled_pairs": int(len(idx)), "mismatches": mism,
+               "verify_ms": round(v_ms, 4), "verified_pairs": int(len(acc_idx)),
+               "verify_pairs_per_s": round(len(acc_idx) / (v_ms / 1e3), 1),
+               "verify_sampled": int(len(vidx)), "verify_mismatches": vmism}
         rows.append(row)
         if (m, e) == (100, 5):
             headline = (row, steps, wall)
         log(f"{m} bp e={e}: {k_s * 1e3:.4f} ms, {n / k_s / 1e9:.2f} G pairs/s, "
-            f"VALU {row['valu_frac']:.3f}, {mism} mismatches of {len(idx)} "
+            f"VALU {row['valu_frac']:.3f}, {mism} mismatches of {len(idx)}; verify "
+            f"{v_ms:.4f} ms for {len(acc_idx)} accepted, {vmism} mismatches "
             f"({time.time() - t:.1f}s)")
         del batch, dp, dr, ps
         torch.cuda.empty_cache()
@@ -549,7 +576,8 @@ def bench_sweep(args, log) -> int:
         "data": "synthetic",
         "config": {"workload": "plain filter sweep: 2^24 pairs of 100 bp for e = 0..10, "
                                "2^25 pairs at 150 bp (e = 3, 7, 15) and 250 bp (e = 5, 12, 25), "
-                               "100 Mbp GC-41% reference"},
+                               "100 Mbp GC-41% reference",
+                   "pairs_per_lane": args.pairs_per_lane},
         "roofline": {"bound": "alu", "kernel": row["kernel"],
                      "achieved": round(row["valu_frac"] * VALU_PEAK_TOPS, 3),
                      "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",

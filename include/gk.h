@@ -283,8 +283,8 @@ int gk_verify(gk_ctx *ctx, const gk_batch *batch, const uint8_t *accept, uint16_
 
 /* Tuning options of a context (they never change results). */
 #define GK_OPT_PAIRS_PER_LANE 1   /* plain filter grid: 0 (default) =
-                                     automatic from e and the read length;
-                                     1 = one pair per lane; k in 2..65535 =
+                                     automatic (currently one pair per
+                                     lane); 1 = one pair per lane; k in 2..65535 =
                                      about k pairs per lane, each lane
                                      keeping its next pair's loads in
                                      flight; 65536 = one residency of the

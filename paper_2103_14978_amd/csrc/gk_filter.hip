@@ -130,12 +130,11 @@ hipError_t launch_wl(const FilterArgs &a, uint32_t pairs_per_lane, hipStream_t s
             continue;
         }
         if (pairs_per_lane == 0) {
-            // Automatic: light pairs (few masks of few words) are bound by the
-            // window gathers and run best with the most waves in flight; heavy
-            // pairs are bound by the VALU and gain from each lane prefetching
-            // its next pair.
-            const uint32_t e = a.e_pair ? 16u : a.e_uniform;
-            pairs_per_lane = (2u * e + 1u) * W >= 60u ? 4u : 1u;
+            // Automatic: one pair per lane.  Measured over 100 bp at e = 0..10
+            // and 150 / 250 bp at 2-10 % thresholds, it beat four pairs per
+            // lane (each lane prefetching its next pair) at every point, light
+            // pairs (gather-bound) and heavy ones (VALU-bound) alike.
+            pairs_per_lane = 1u;
         }
         if (pairs_per_lane == 1) {
             hipLaunchKernelGGL((k_filter_single<W, L>), dim3((uint32_t)full), dim3(256), 0, s, c);

@@ -61,7 +61,8 @@ struct gk_ctx {
     hipGraphExec_t graph_exec = nullptr;
     std::vector<uint8_t> graph_key;
     HostPipe host;                            // gk_filter_host
-    uint32_t *d_verify_list = nullptr;        // gk_verify: selected pairs
+    uint32_t *d_verify_list = nullptr;        // gk_verify: selected pairs (verify_cap
+                                              // words), then per-workgroup counts
     uint32_t *d_verify_count = nullptr;
     uint64_t verify_cap = 0;
 };

@@ -25,29 +25,69 @@
 namespace gkd {
 namespace {
 
-// One column step of the banded edit distance.  bh, bl: the band's read-plane
-// bits (bit k = read base j - e + k - 1, 0-based, for text column j); th, tl:
-// the text base's code bits as all-zero / all-one masks.
-template <typename T>
-__device__ __forceinline__ void band_step(T bh, T bl, T th, T tl, T top, T keep, uint32_t e,
-                                          T &vp, T &vn, uint32_t &score)
+// A 64-bit band word kept as two 32-bit halves, so that chains of logic
+// operations on it map onto 3-input logic instructions per half (whole 64-bit
+// values get split into halves only after that combining is done).
+struct B64 {
+    uint32_t lo, hi;
+};
+__device__ __forceinline__ B64 operator&(B64 a, B64 b) { return {a.lo & b.lo, a.hi & b.hi}; }
+__device__ __forceinline__ B64 operator|(B64 a, B64 b) { return {a.lo | b.lo, a.hi | b.hi}; }
+__device__ __forceinline__ B64 operator^(B64 a, B64 b) { return {a.lo ^ b.lo, a.hi ^ b.hi}; }
+__device__ __forceinline__ B64 operator~(B64 a) { return {~a.lo, ~a.hi}; }
+__device__ __forceinline__ B64 operator+(B64 a, B64 b)
 {
-    const T eq = ~((bh ^ th) | (bl ^ tl));
-    // slide the band down one row; the new bottom row steps +1
-    vp = ((vp >> 1) & keep) | top;
-    vn = (vn >> 1) & keep;
-    const T xv = eq | vn;
-    const T xh = (((eq & vp) + vp) ^ vp) | eq;
-    score += 1u - (uint32_t)(((xh | vn) >> e) & 1u);   // diagonal step
-    T ph = vn | ~(xh | vp);
-    T mh = vp & xh;
-    ph = (ph << 1) | 1u;                 // the row above the band steps +1
-    mh = mh << 1;
-    vp = mh | ~(xv | ph);
-    vn = ph & xv;
+    const uint64_t s = (((uint64_t)a.hi << 32) | a.lo) + (((uint64_t)b.hi << 32) | b.lo);
+    return {(uint32_t)s, (uint32_t)(s >> 32)};
 }
 
-// 32 (T = uint32_t) or 64 (T = uint64_t) bits of [a | b | c] from bit s of a.
+template <typename T> __device__ __forceinline__ T from64(uint64_t v);
+template <> __device__ __forceinline__ uint32_t from64<uint32_t>(uint64_t v) { return (uint32_t)v; }
+template <> __device__ __forceinline__ B64 from64<B64>(uint64_t v)
+{
+    return {(uint32_t)v, (uint32_t)(v >> 32)};
+}
+
+// all-zero / all-one mask of one text code bit
+template <typename T> __device__ __forceinline__ T broadcast(uint32_t m);
+template <> __device__ __forceinline__ uint32_t broadcast<uint32_t>(uint32_t m) { return m; }
+template <> __device__ __forceinline__ B64 broadcast<B64>(uint32_t m) { return {m, m}; }
+
+__device__ __forceinline__ uint32_t shr1(uint32_t x) { return x >> 1; }
+__device__ __forceinline__ B64 shr1(B64 x) { return {funnel(x.hi, x.lo, 1), x.hi >> 1}; }
+
+// bit e of x; e <= 31 in both widths (the wide band serves 16 <= e <= 31)
+__device__ __forceinline__ uint32_t bit_at(uint32_t x, uint32_t e) { return (x >> e) & 1u; }
+__device__ __forceinline__ uint32_t bit_at(B64 x, uint32_t e) { return (x.lo >> e) & 1u; }
+
+// One column step of the banded edit distance.  bh, bl: the band's read-plane
+// bits (bit k = read base j - e + k - 1, 0-based, for text column j); th, tl:
+// the text base's code bits as all-zero / all-one masks.  vp, vn come in
+// already slid down one row into this column's band (bit 2e, the new bottom
+// row, steps +1) and leave slid into the next column's: the slide's shift
+// right cancels the shift left of the horizontal deltas, so the next column's
+// vertical deltas at band row k read the horizontal deltas of row k and the
+// XV bit of row k + 1 directly.  Bits above 2e may hold anything in eq, xh, ph
+// and mh: carries and shifts only move information upward there, and the
+// masks keep them out of vp and vn.
+template <typename T>
+__device__ __forceinline__ void band_step(T bh, T bl, T th, T tl, T top, T keep, uint32_t e,
+                                          T &vp, T &vn, uint32_t &flat)
+{
+    const T eq = ~((bh ^ th) | (bl ^ tl));
+    const T xh = (((eq & vp) + vp) ^ vp) | eq;
+    flat += bit_at(xh | vn, e);          // the diagonal did not step +1
+    // Horizontal deltas +1 / -1 of the band rows.  The row above the band
+    // (+1) would only enter bit 0 of this column's new vertical deltas, which
+    // the slide drops.
+    const T ph = vn | ~(xh | vp);
+    const T mh = vp & xh;
+    const T xv1 = shr1(eq | vn);         // XV of the next column's band rows
+    vp = ((mh | ~(xv1 | ph)) & keep) | top;
+    vn = ph & xv1 & keep;
+}
+
+// 32 (T = uint32_t) or 64 (T = B64) bits of [a | b | c] from bit s of a.
 template <typename T>
 __device__ __forceinline__ T bits_from(uint32_t a, uint32_t b, uint32_t c, uint32_t s)
 {
@@ -55,7 +95,7 @@ __device__ __forceinline__ T bits_from(uint32_t a, uint32_t b, uint32_t c, uint3
     if constexpr (sizeof(T) == 4)
         return lo;
     else
-        return ((uint64_t)funnel(c, b, s) << 32) | lo;
+        return B64{lo, funnel(c, b, s)};
 }
 
 // Read bases are taken from [32 zero bits | plane words 0..W-1 | zeros]: for
@@ -68,11 +108,14 @@ __device__ __forceinline__ uint32_t band_distance(const uint32_t (&rh)[W], const
                                                   const uint32_t (&gh)[W], const uint32_t (&gl)[W],
                                                   uint32_t m, uint32_t e)
 {
-    const T top = (T)1 << (2 * e);                 // band row 2e: enters each column
-    const T keep = top - 1;                        // band rows 0 .. 2e-1 after a slide
-    T vn = ((T)2 << e) - 1;                        // column 0: rows -e..0 step -1,
-    T vp = (top | keep) & ~vn;                     //           rows 1..e step +1
-    uint32_t score = 0;                            // D[j][j]
+    const uint64_t top64 = 1ull << (2 * e);        // band row 2e: enters each column
+    const uint64_t keep64 = top64 - 1;             // band rows 0 .. 2e-1 after a slide
+    const uint64_t vn0 = (2ull << e) - 1;          // column 0: rows -e..0 step -1,
+    const uint64_t vp0 = (top64 | keep64) & ~vn0;  //           rows 1..e step +1
+    const T top = from64<T>(top64), keep = from64<T>(keep64);
+    T vp = from64<T>(((vp0 >> 1) & keep64) | top64);   // slid into column 1's band
+    T vn = from64<T>((vn0 >> 1) & keep64);
+    uint32_t flat = 0;                             // columns j where D[j][j] = D[j-1][j-1]
 #pragma unroll
     for (int blk = 0; blk < W; ++blk) {
         const uint32_t h0 = blk >= 1 ? rh[blk - 1] : 0u, l0 = blk >= 1 ? rl[blk - 1] : 0u;
@@ -85,18 +128,19 @@ __device__ __forceinline__ uint32_t band_distance(const uint32_t (&rh)[W], const
         for (int c = 0; c < split; ++c) {          // band starts in read word blk - 1
             const uint32_t s = (uint32_t)c + 32u - e;
             band_step<T>(bits_from<T>(h0, h1, h2, s), bits_from<T>(l0, l1, l2, s),
-                         (T)(int32_t)__builtin_amdgcn_sbfe(th_w, c, 1),
-                         (T)(int32_t)__builtin_amdgcn_sbfe(tl_w, c, 1), top, keep, e, vp, vn,
-                         score);
+                         broadcast<T>(__builtin_amdgcn_sbfe(th_w, c, 1)),
+                         broadcast<T>(__builtin_amdgcn_sbfe(tl_w, c, 1)), top, keep, e, vp, vn,
+                         flat);
         }
         for (int c = split; c < cols; ++c) {       // band starts in read word blk
             const uint32_t s = (uint32_t)c - e;
             band_step<T>(bits_from<T>(h1, h2, h3, s), bits_from<T>(l1, l2, l3, s),
-                         (T)(int32_t)__builtin_amdgcn_sbfe(th_w, c, 1),
-                         (T)(int32_t)__builtin_amdgcn_sbfe(tl_w, c, 1), top, keep, e, vp, vn,
-                         score);
+                         broadcast<T>(__builtin_amdgcn_sbfe(th_w, c, 1)),
+                         broadcast<T>(__builtin_amdgcn_sbfe(tl_w, c, 1)), top, keep, e, vp, vn,
+                         flat);
         }
     }
+    const uint32_t score = m - flat;               // D[m][m]: each diagonal step is 0 or +1
     return score < e + 1u ? score : e + 1u;
 }
 
@@ -114,69 +158,156 @@ __global__ __launch_bounds__(256) void k_verify(FilterArgs a, const uint32_t *li
         if (p.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p, d, m) == PAIR_OK) {
             uint32_t gh[W], gl[W], rh[W], rl[W];
             pair_planes<W, L>(p, d, m, gh, gl, rh, rl);
-            out = p.e <= 15u ? band_distance<W, uint32_t>(rh, rl, gh, gl, m, p.e)
-                             : band_distance<W, uint64_t>(rh, rl, gh, gl, m, p.e);
+            // When every active lane has the same threshold and length (always
+            // so for one read length and a uniform e), the band's shifts and
+            // trip counts come from scalar registers.
+            const uint32_t e0 = __builtin_amdgcn_readfirstlane(p.e);
+            const uint32_t m0 = __builtin_amdgcn_readfirstlane(m);
+            if (__ballot(p.e != e0 || m != m0) == 0ull)
+                out = e0 <= 15u ? band_distance<W, uint32_t>(rh, rl, gh, gl, m0, e0)
+                                : band_distance<W, B64>(rh, rl, gh, gl, m0, e0);
+            else
+                out = p.e <= 15u ? band_distance<W, uint32_t>(rh, rl, gh, gl, m, p.e)
+                                 : band_distance<W, B64>(rh, rl, gh, gl, m, p.e);
         }
         dist[i] = (uint16_t)out;
     }
 }
 
-__global__ void k_verify_reset(uint32_t *count) { *count = 0u; }
+// Listing the pairs to verify (accept[i] == GK_ACCEPT, or every pair when
+// accept is NULL) in pair order, without a contended counter: a workgroup
+// covers 4096 consecutive pairs, 16 per lane (one 16-byte load of accept when
+// VEC); k_select_count stores each workgroup's count, k_select_scan turns the
+// counts into offsets (and the total into *count), k_select_write puts each
+// workgroup's pairs at its offset through LDS.  VEC needs accept and dist
+// aligned to 16 bytes; the host checks.
+constexpr uint32_t SEL_PER_LANE = 16u, SEL_PER_GROUP = 256u * SEL_PER_LANE;
 
-// Lists the pairs to verify (accept[i] == GK_ACCEPT, or every pair when
-// accept is NULL) in pair order within each workgroup's contiguous range, with
-// one atomic per workgroup: a first pass counts the range's selected pairs, a
-// second writes them.  The other pairs get GK_EST_NONE.
-__global__ __launch_bounds__(256) void k_verify_select(const uint8_t *accept, uint32_t n,
-                                                       uint32_t *list, uint32_t *count,
-                                                       uint16_t *dist)
+// Bit j of the result: pair i0 + j is listed.  With fill, the 16 dist entries
+// are set to GK_EST_NONE first (k_verify overwrites the listed ones later).
+template <bool VEC>
+__device__ __forceinline__ uint32_t select_bits(const uint8_t *accept, uint32_t n, uint32_t i0,
+                                                uint16_t *dist, bool fill)
+{
+    const uint32_t valid = i0 < n ? (n - i0 < SEL_PER_LANE ? n - i0 : SEL_PER_LANE) : 0u;
+    uint32_t sel = 0;
+    if (accept == nullptr) {
+        sel = valid == SEL_PER_LANE ? 0xFFFFu : ((1u << valid) - 1u);
+    } else if (VEC && valid == SEL_PER_LANE) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(accept + i0);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+                sel |= (((w[q] >> (8 * b)) & 0xFFu) == GK_ACCEPT ? 1u : 0u) << (4 * q + b);
+        if (fill) {
+            const uint4 none = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+            reinterpret_cast<uint4 *>(dist + i0)[0] = none;
+            reinterpret_cast<uint4 *>(dist + i0)[1] = none;
+        }
+    } else {
+        for (uint32_t j = 0; j < valid; ++j) {
+            sel |= (accept[i0 + j] == GK_ACCEPT ? 1u : 0u) << j;
+            if (fill)
+                dist[i0 + j] = (uint16_t)GK_EST_NONE;
+        }
+    }
+    return sel;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_select_count(const uint8_t *accept, uint32_t n,
+                                                      uint32_t *group_count, uint16_t *dist)
 {
     __shared__ uint32_t wave_sum[4];
-    __shared__ uint32_t base;
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
-    const uint32_t per = ((n + gridDim.x - 1) / gridDim.x + 255u) & ~255u;
-    const uint32_t lo = blockIdx.x * per;
-    const uint32_t hi = lo + per < n ? lo + per : n;
-
-    uint32_t c = 0;
-    for (uint32_t i = lo + threadIdx.x; i < hi; i += 256u) {
-        const bool sel = accept == nullptr || accept[i] == GK_ACCEPT;
-        c += sel ? 1u : 0u;
-        if (!sel)
-            dist[i] = (uint16_t)GK_EST_NONE;
-    }
+    const uint32_t i0 = blockIdx.x * SEL_PER_GROUP + threadIdx.x * SEL_PER_LANE;
+    uint32_t c = (uint32_t)__popc(select_bits<VEC>(accept, n, i0, dist, true));
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1)
         c += __shfl_xor(c, o, 64);
     if (lane == 0u)
         wave_sum[wave] = c;
     __syncthreads();
-    if (threadIdx.x == 0u) {
-        const uint32_t total = wave_sum[0] + wave_sum[1] + wave_sum[2] + wave_sum[3];
-        base = total ? atomicAdd(count, total) : 0u;
+    if (threadIdx.x == 0u)
+        group_count[blockIdx.x] = wave_sum[0] + wave_sum[1] + wave_sum[2] + wave_sum[3];
+}
+
+// One workgroup of 1024 lanes: exclusive prefix sums of groups (<= 2^18)
+// counts in place, and the total into *count.
+__global__ __launch_bounds__(1024) void k_select_scan(uint32_t *group_count, uint32_t groups,
+                                                      uint32_t *count)
+{
+    __shared__ uint32_t wave_sum[16];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t per = (groups + 1023u) / 1024u;
+    const uint32_t lo = threadIdx.x * per;
+    const uint32_t hi = lo + per < groups ? lo + per : groups;
+    uint32_t sum = 0;
+    for (uint32_t i = lo; i < hi; ++i)
+        sum += group_count[i];
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o)
+            incl += t;
     }
+    if (lane == 63u)
+        wave_sum[wave] = incl;
     __syncthreads();
-    uint32_t run = base;
-    for (uint32_t start = lo; start < hi; start += 256u) {     // uniform per block
-        const uint32_t i = start + threadIdx.x;
-        const bool sel = i < hi && (accept == nullptr || accept[i] == GK_ACCEPT);
-        const unsigned long long mask = __ballot(sel);
-        __syncthreads();                 // wave_sum of the previous step is read
-        if (lane == 0u)
-            wave_sum[wave] = (uint32_t)__popcll(mask);
-        __syncthreads();
-        uint32_t before = 0;
-        for (uint32_t w = 0; w < wave; ++w)
-            before += wave_sum[w];
-        if (sel)
-            list[run + before + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull))] = i;
-        run += wave_sum[0] + wave_sum[1] + wave_sum[2] + wave_sum[3];
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w)
+        before += wave_sum[w];
+    uint32_t run = before + incl - sum;
+    for (uint32_t i = lo; i < hi; ++i) {
+        const uint32_t v = group_count[i];
+        group_count[i] = run;
+        run += v;
     }
+    if (threadIdx.x == 1023u)
+        *count = before + incl;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_select_write(const uint8_t *accept, uint32_t n,
+                                                      const uint32_t *group_offset,
+                                                      uint32_t *list)
+{
+    __shared__ uint32_t stage[SEL_PER_GROUP];
+    __shared__ uint32_t wave_sum[4];
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    const uint32_t i0 = blockIdx.x * SEL_PER_GROUP + threadIdx.x * SEL_PER_LANE;
+    const uint32_t sel = select_bits<VEC>(accept, n, i0, nullptr, false);
+    const uint32_t c = (uint32_t)__popc(sel);
+    uint32_t incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o)
+            incl += t;
+    }
+    if (lane == 63u)
+        wave_sum[wave] = incl;
+    __syncthreads();
+    const uint32_t total = wave_sum[0] + wave_sum[1] + wave_sum[2] + wave_sum[3];
+    uint32_t at = incl - c;
+    for (uint32_t w = 0; w < wave; ++w)
+        at += wave_sum[w];
+#pragma unroll
+    for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+        if (sel & (1u << j))
+            stage[at++] = i0 + j;
+    __syncthreads();
+    const uint32_t base = group_offset[blockIdx.x];
+    for (uint32_t t = threadIdx.x; t < total; t += 256u)
+        list[base + t] = stage[t];
 }
 
 template <int W, int L>
 hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, uint32_t *list,
-                     uint32_t *count, int cus, hipStream_t s)
+                     uint32_t *groups_buf, uint32_t *count, int cus, hipStream_t s)
 {
     static int per_cu = -1;
     if (per_cu < 0) {
@@ -199,11 +330,22 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
         c.accept_bits = nullptr;
         const uint8_t *acc = accept ? accept + first : nullptr;
         uint16_t *out = dist + first;
-        hipLaunchKernelGGL(k_verify_reset, dim3(1), dim3(1), 0, s, count);
         const uint64_t want = (n + 255) / 256;
-        const uint32_t sel_blocks = (uint32_t)(want < (uint64_t)cus * 4 ? want : (uint64_t)cus * 4);
-        hipLaunchKernelGGL(k_verify_select, dim3(sel_blocks), dim3(256), 0, s, acc, (uint32_t)n,
-                           list, count, out);
+        const uint32_t groups = (uint32_t)((n + SEL_PER_GROUP - 1) / SEL_PER_GROUP);
+        const bool vec = ((uintptr_t)acc & 15u) == 0 && ((uintptr_t)out & 15u) == 0;
+        if (vec)
+            hipLaunchKernelGGL(k_select_count<true>, dim3(groups), dim3(256), 0, s, acc,
+                               (uint32_t)n, groups_buf, out);
+        else
+            hipLaunchKernelGGL(k_select_count<false>, dim3(groups), dim3(256), 0, s, acc,
+                               (uint32_t)n, groups_buf, out);
+        hipLaunchKernelGGL(k_select_scan, dim3(1), dim3(1024), 0, s, groups_buf, groups, count);
+        if (vec)
+            hipLaunchKernelGGL(k_select_write<true>, dim3(groups), dim3(256), 0, s, acc,
+                               (uint32_t)n, groups_buf, list);
+        else
+            hipLaunchKernelGGL(k_select_write<false>, dim3(groups), dim3(256), 0, s, acc,
+                               (uint32_t)n, groups_buf, list);
         const uint64_t vb = want < (uint64_t)cus * per_cu ? want : (uint64_t)cus * per_cu;
         hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vb), dim3(256), 0, s, c, list, count,
                            out);
@@ -216,25 +358,25 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
 
 template <int L>
 hipError_t verify_l(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, uint32_t *list,
-                    uint32_t *count, uint32_t words, int cus, hipStream_t s)
+                    uint32_t *groups_buf, uint32_t *count, uint32_t words, int cus, hipStream_t s)
 {
     switch (words) {
-    case 1: return verify_wl<1, L>(a, accept, dist, list, count, cus, s);
-    case 2: return verify_wl<2, L>(a, accept, dist, list, count, cus, s);
-    case 3: return verify_wl<3, L>(a, accept, dist, list, count, cus, s);
-    case 4: return verify_wl<4, L>(a, accept, dist, list, count, cus, s);
-    case 5: return verify_wl<5, L>(a, accept, dist, list, count, cus, s);
-    case 6: return verify_wl<6, L>(a, accept, dist, list, count, cus, s);
-    case 7: return verify_wl<7, L>(a, accept, dist, list, count, cus, s);
-    case 8: return verify_wl<8, L>(a, accept, dist, list, count, cus, s);
-    case 9: return verify_wl<9, L>(a, accept, dist, list, count, cus, s);
-    case 10: return verify_wl<10, L>(a, accept, dist, list, count, cus, s);
-    case 11: return verify_wl<11, L>(a, accept, dist, list, count, cus, s);
-    case 12: return verify_wl<12, L>(a, accept, dist, list, count, cus, s);
-    case 13: return verify_wl<13, L>(a, accept, dist, list, count, cus, s);
-    case 14: return verify_wl<14, L>(a, accept, dist, list, count, cus, s);
-    case 15: return verify_wl<15, L>(a, accept, dist, list, count, cus, s);
-    case 16: return verify_wl<16, L>(a, accept, dist, list, count, cus, s);
+    case 1: return verify_wl<1, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 2: return verify_wl<2, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 3: return verify_wl<3, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 4: return verify_wl<4, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 5: return verify_wl<5, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 6: return verify_wl<6, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 7: return verify_wl<7, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 8: return verify_wl<8, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 9: return verify_wl<9, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 10: return verify_wl<10, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 11: return verify_wl<11, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 12: return verify_wl<12, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 13: return verify_wl<13, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 14: return verify_wl<14, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 15: return verify_wl<15, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 16: return verify_wl<16, L>(a, accept, dist, list, groups_buf, count, cus, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -242,12 +384,13 @@ hipError_t verify_l(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, 
 }  // namespace
 
 hipError_t launch_verify(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
-                         uint32_t *list, uint32_t *count, uint32_t words, uint32_t layout,
-                         int cus, hipStream_t s)
+                         uint32_t *list, uint32_t *groups, uint32_t *count, uint32_t words,
+                         uint32_t layout, int cus, hipStream_t s)
 {
     return layout == GK_READS_INTERLEAVED
-               ? verify_l<GK_READS_INTERLEAVED>(a, accept, dist, list, count, words, cus, s)
-               : verify_l<GK_READS_SPLIT>(a, accept, dist, list, count, words, cus, s);
+               ? verify_l<GK_READS_INTERLEAVED>(a, accept, dist, list, groups, count, words, cus,
+                                                s)
+               : verify_l<GK_READS_SPLIT>(a, accept, dist, list, groups, count, words, cus, s);
 }
 
 }  // namespace gkd

@@ -96,6 +96,24 @@ def test_verify_thresholds_and_lengths(gkctx):
     assert np.array_equal(d, want)
 
 
+@pytest.mark.parametrize("m,e", [(100, 0), (100, 5), (37, 3), (100, 15), (150, 16),
+                                 (250, 25), (512, 31), (300, 20)])
+def test_verify_uniform_waves(gkctx, m, e):
+    """One length and one threshold for the whole batch: every wave takes the
+    path whose band shifts and trip counts are scalar (both band widths)."""
+    rng = np.random.default_rng(1000 + m + e)
+    ref = gen.c0_reference()
+    gk.gk_load_reference(gkctx, ref)
+    reads, off, pr, pos, _ = edited_pairs(rng, ref, 3000, max_len=m, min_len=m)
+    ev = np.full(len(pos), e, np.uint8)
+    say(f"case: verify uniform m={m} e={e}")
+    d = verify(gkctx, reads, off, pr, pos, ev, m)
+    want = oracle_dist(ref, reads, off, pr, pos, ev)
+    bad = np.nonzero(d != want)[0]
+    assert len(bad) == 0, f"{len(bad)} differ; first {bad[0]}: gpu {d[bad[0]]} oracle {want[bad[0]]}"
+    assert np.any(d <= e) and np.any(d == e + 1)
+
+
 def test_verify_after_filter_and_status(gkctx):
     """Only GK_ACCEPT pairs are verified; rejected, undefined (unknown base,
     window past the end) and invalid pairs give GK_EST_NONE."""
@@ -125,6 +143,39 @@ def test_verify_after_filter_and_status(gkctx):
     e = np.array([3, 3, 3, 3, 3], np.uint8)
     d = verify(gkctx, reads, off, pr, pos, e, 128)
     assert list(d) == [0] + [gk.GK_EST_NONE] * 4
+
+
+@pytest.mark.parametrize("k,doff", [(1, 1), (3, 8), (16, 8)])
+def test_verify_unaligned_buffers(gkctx, k, doff):
+    """accept and dist at offsets that are not 16-byte aligned take the
+    byte-wise select; an aligned offset takes the vector one.  Both list the
+    same pairs: distances for the accepted, GK_EST_NONE for the rest, and
+    nothing written outside dist."""
+    ref = gen.c1_reference(2_000_000)
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c1_pairs(ref, 5, n_pairs=(1 << 15) + 37)
+    n = ps.n_pairs
+    say(f"case: verify buffer offsets accept +{k} B, dist +{2 * doff} B")
+    dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=100)
+    dp = device.upload_pairs(None, ps.cand_pos)
+    gk.gk_filter(gkctx, device.batch_for(dr, dp, e_uniform=5, max_read_len=100), None)
+    dp2 = device.upload_pairs(ps.pair_read[k:], ps.cand_pos[k:])
+    b2 = device.batch_for(dr, dp2, e_uniform=5, max_read_len=100)
+    dist_full = torch.full((n + doff + 1,), 0x1234, dtype=torch.int16, device="cuda")
+    acc_view = dp.accept[k:]
+    dist_view = dist_full[doff:doff + n - k]
+    gk.gk_verify(gkctx, b2, acc_view, dist_view, None)
+    torch.cuda.synchronize()
+    a, _ = device.results(dp)
+    a = a[k:]
+    full = dist_full.cpu().numpy().view(np.uint16)
+    assert np.all(full[:doff] == 0x1234) and np.all(full[doff + n - k:] == 0x1234)
+    d = full[doff:doff + n - k]
+    acc = a == gk.GK_ACCEPT
+    assert np.all(d[~acc] == gk.GK_EST_NONE)
+    want = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[k:][acc],
+                                    ps.cand_pos[k:][acc], 5, n_threads=gen.default_threads())
+    assert np.array_equal(d[acc], want)
 
 
 def test_verify_errors(gkctx):
