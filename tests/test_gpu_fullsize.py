@@ -154,3 +154,77 @@ def test_config4_2bit_reference(gkctx):
         ra, rs = run_oracle(ref, p.reads, p.read_off, p.pair_read, p.cand_pos, p.meta["e"])
         assert_same(a, s, ra, rs, f"config4 2bit request {k}")
         assert np.any(a == gk.GK_UNDEFINED)
+
+
+def test_beyond_2e30_pairs(gkctx):
+    """2^30 + 4133 pairs over 4096 reads: every entry point splits such a batch
+    into launches of 2^30 pairs.  Plain launch against the oracle on the pairs
+    around the split, the tail and a random sample; the mixed launch (with its
+    accept bits) equal to the plain one on every pair; gk_verify on the
+    sampled pairs against the oracle's distances."""
+    import oracle
+    n = (1 << 30) + 4133
+    m, e, n_reads = 100, 5, 4096
+    rng = np.random.default_rng(2030)
+    ref = gen.c1_reference(20_000_000)
+    gk.gk_load_reference(gkctx, ref)
+    origins = rng.integers(8, len(ref) - m - 8, n_reads)
+    seqs = []
+    for o in origins:
+        s = ref[o:o + m].copy()
+        q = rng.integers(0, m, int(rng.integers(0, 8)))
+        s[q] = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, len(q))]
+        seqs.append(s.tobytes())
+    from gpu_cases import concat_reads
+    reads, off = concat_reads(seqs)
+    say(f"case: beyond 2^30, n_pairs={n}")
+    pr = np.arange(n, dtype=np.uint32)
+    np.remainder(pr, np.uint32(n_reads), out=pr)
+    pos = rng.integers(0, len(ref) - m, n, dtype=np.uint32)
+    step = 1 << 26
+    for s0 in range(0, n, step):
+        sl = slice(s0, min(n, s0 + step))
+        idx = np.arange(sl.start, sl.stop, dtype=np.uint32)
+        true = (idx % np.uint32(10)) < 3          # 30% of pairs at their read's origin
+        pos[sl][true] = (origins[pr[sl][true]] + (idx[true] % 5).astype(np.int64) - 2).astype(
+            np.uint32)
+    dr = device.encode_reads(gkctx, reads, off, max_len=m)
+    dp = device.upload_pairs(pr, pos, with_bits=True)
+    b = device.batch_for(dr, dp, e_uniform=e, max_read_len=m)
+    gk.gk_filter(gkctx, b, None)
+    torch.cuda.synchronize()
+    a, s = device.results(dp)
+    # every pair is ACCEPT or REJECT, est <= m, accept iff est <= e
+    assert int(a.max()) <= 1 and int(s.max()) <= m
+    assert np.array_equal(a == 1, s <= e)
+    split = 1 << 30
+    idx = np.unique(np.concatenate([
+        np.arange(split - 2048, split + 2048), np.arange(n - 600, n),
+        rng.choice(n, 1 << 15, replace=False)]))
+    ra, rs = run_oracle(ref, reads, off, pr[idx], pos[idx], e)
+    assert_same(a[idx], s[idx], ra, rs, "beyond 2^30 plain sample")
+    assert 0.2 < np.mean(a[idx] == 1) < 0.5
+    for opt, val in ((gk.GK_OPT_MIXED_TILE, 4096), (gk.GK_OPT_MIXED_PAIRS_PER_LANE, 1),
+                     (gk.GK_OPT_MIXED_SORT_E, 1), (gk.GK_OPT_MIXED_BLOCKS_PER_CU, 0)):
+        gk.gk_set_option(gkctx, opt, val)
+    dp.accept.fill_(0xEE)
+    gk.gk_filter_mixed(gkctx, b, None)
+    torch.cuda.synchronize()
+    a2, s2 = device.results(dp)
+    assert np.array_equal(a2, a) and np.array_equal(s2, s), "mixed differs from plain"
+    del a2, s2
+    bits = dp.accept_bits.cpu().numpy().view(np.uint8)
+    got = np.unpackbits(bits[:(n + 7) // 8], bitorder="little")[:n]
+    assert np.array_equal(got[idx].astype(bool), (a[idx] == 1) | (a[idx] == 2))
+    del bits, got
+    dist = torch.empty(n, dtype=torch.int16, device="cuda")
+    gk.gk_verify(gkctx, b, dp.accept, dist, None)
+    torch.cuda.synchronize()
+    d = dist[torch.from_numpy(idx).cuda()].cpu().numpy().view(np.uint16)
+    acc = a[idx] == gk.GK_ACCEPT
+    assert np.all(d[~acc] == gk.GK_EST_NONE)
+    want = oracle.levenshtein_batch(reads, off, ref, pr[idx][acc], pos[idx][acc], e,
+                                    n_threads=gen.default_threads())
+    assert np.array_equal(d[acc], want)
+    del dist, dp, dr, b, pr, pos, a, s
+    torch.cuda.empty_cache()
