@@ -71,12 +71,10 @@ __device__ __forceinline__ uint32_t bit_at(B64 x, uint32_t e) { return (x.lo >> 
 // and mh: carries and shifts only move information upward there, and the
 // masks keep them out of vp and vn.
 template <typename T>
-__device__ __forceinline__ void band_step(T bh, T bl, T th, T tl, T top, T keep, uint32_t e,
-                                          T &vp, T &vn, uint32_t &flat)
+__device__ __forceinline__ T band_column(T eq, T top, T keep, T &vp, T &vn)
 {
-    const T eq = ~((bh ^ th) | (bl ^ tl));
     const T xh = (((eq & vp) + vp) ^ vp) | eq;
-    flat += bit_at(xh | vn, e);          // the diagonal did not step +1
+    const T diag = xh | vn;              // bit e: the diagonal did not step +1
     // Horizontal deltas +1 / -1 of the band rows.  The row above the band
     // (+1) would only enter bit 0 of this column's new vertical deltas, which
     // the slide drops.
@@ -85,6 +83,15 @@ __device__ __forceinline__ void band_step(T bh, T bl, T th, T tl, T top, T keep,
     const T xv1 = shr1(eq | vn);         // XV of the next column's band rows
     vp = ((mh | ~(xv1 | ph)) & keep) | top;
     vn = ph & xv1 & keep;
+    return diag;
+}
+
+template <typename T>
+__device__ __forceinline__ void band_step(T bh, T bl, T th, T tl, T top, T keep, uint32_t e,
+                                          T &vp, T &vn, uint32_t &flat)
+{
+    const T eq = ~((bh ^ th) | (bl ^ tl));
+    flat += bit_at(band_column(eq, top, keep, vp, vn), e);
 }
 
 // 32 (T = uint32_t) or 64 (T = B64) bits of [a | b | c] from bit s of a.
@@ -144,33 +151,147 @@ __device__ __forceinline__ uint32_t band_distance(const uint32_t (&rh)[W], const
     return score < e + 1u ? score : e + 1u;
 }
 
+// Two pairs with the same length m and the same e <= 7 in one 32-bit word:
+// pair 0's band in bits 0..15, pair 1's in bits 16..31.  A band of 2e+1 <= 15
+// rows keeps (eq & vp) + vp below 2^(2e+2) <= 2^16, so no carry crosses into
+// the other pair's half; the shift right moves bit 16 into half 0's bit 15,
+// above its band, where the masks clear it.  Both pairs share every logic
+// instruction; only the gathers of their read bits and text bits are
+// separate (byte permutes put the two halves together).  Returns
+// dist0 | dist1 << 16.
+__device__ __forceinline__ uint32_t halves(uint32_t hi_src, uint32_t lo_src)
+{
+    return __builtin_amdgcn_perm(hi_src, lo_src, 0x05040100u);   // {lo_src[15:0], hi_src[15:0]}
+}
+
+// One column of both pairs: h0, l0 / h1, l1 are 32 read-plane bits from each
+// pair's band start; the text bits are bit c of each pair's window words.
+__device__ __forceinline__ void band_step2(uint32_t h0, uint32_t l0, uint32_t h1, uint32_t l1,
+                                           uint32_t t0h, uint32_t t0l, uint32_t t1h,
+                                           uint32_t t1l, int c, uint32_t top, uint32_t keep,
+                                           uint32_t e, uint32_t &vp, uint32_t &vn,
+                                           uint32_t &flat)
+{
+    const uint32_t bh = halves(h1, h0), bl = halves(l1, l0);
+    const uint32_t th = halves((uint32_t)__builtin_amdgcn_sbfe(t1h, c, 1),
+                               (uint32_t)__builtin_amdgcn_sbfe(t0h, c, 1));
+    const uint32_t tl = halves((uint32_t)__builtin_amdgcn_sbfe(t1l, c, 1),
+                               (uint32_t)__builtin_amdgcn_sbfe(t0l, c, 1));
+    const uint32_t eq = ~((bh ^ th) | (bl ^ tl));
+    flat += (band_column<uint32_t>(eq, top, keep, vp, vn) >> e) & 0x00010001u;
+}
+
+template <int W>
+__device__ __forceinline__ uint32_t band_distance2(
+    const uint32_t (&rh0)[W], const uint32_t (&rl0)[W], const uint32_t (&gh0)[W],
+    const uint32_t (&gl0)[W], const uint32_t (&rh1)[W], const uint32_t (&rl1)[W],
+    const uint32_t (&gh1)[W], const uint32_t (&gl1)[W], uint32_t m, uint32_t e)
+{
+    const uint32_t top1 = 1u << (2 * e), keep1 = top1 - 1u;
+    const uint32_t vn0 = (2u << e) - 1u, vp0 = (top1 | keep1) & ~vn0;
+    const uint32_t vps = ((vp0 >> 1) & keep1) | top1, vns = (vn0 >> 1) & keep1;
+    const uint32_t top = top1 | (top1 << 16), keep = keep1 | (keep1 << 16);
+    uint32_t vp = vps | (vps << 16), vn = vns | (vns << 16);
+    uint32_t flat = 0;                   // two 16-bit counters
+#pragma unroll
+    for (int blk = 0; blk < W; ++blk) {
+        const uint32_t a0 = blk >= 1 ? rh0[blk - 1] : 0u, b0 = blk >= 1 ? rl0[blk - 1] : 0u;
+        const uint32_t c0 = blk >= 1 ? rh1[blk - 1] : 0u, d0 = blk >= 1 ? rl1[blk - 1] : 0u;
+        const uint32_t a1 = rh0[blk], b1 = rl0[blk], c1 = rh1[blk], d1 = rl1[blk];
+        const uint32_t a2 = blk + 1 < W ? rh0[blk + 1] : 0u, b2 = blk + 1 < W ? rl0[blk + 1] : 0u;
+        const uint32_t c2 = blk + 1 < W ? rh1[blk + 1] : 0u, d2 = blk + 1 < W ? rl1[blk + 1] : 0u;
+        const int cols = (int)m - 32 * blk < 32 ? (int)m - 32 * blk : 32;
+        const int split = (int)e < cols ? (int)e : cols;
+        const uint32_t t0h = gh0[blk], t0l = gl0[blk], t1h = gh1[blk], t1l = gl1[blk];
+        for (int c = 0; c < split; ++c)          // band starts in read word blk - 1
+            band_step2(funnel(a1, a0, (uint32_t)c + 32u - e), funnel(b1, b0, (uint32_t)c + 32u - e),
+                       funnel(c1, c0, (uint32_t)c + 32u - e), funnel(d1, d0, (uint32_t)c + 32u - e),
+                       t0h, t0l, t1h, t1l, c, top, keep, e, vp, vn, flat);
+        for (int c = split; c < cols; ++c)       // band starts in read word blk
+            band_step2(funnel(a2, a1, (uint32_t)c - e), funnel(b2, b1, (uint32_t)c - e),
+                       funnel(c2, c1, (uint32_t)c - e), funnel(d2, d1, (uint32_t)c - e),
+                       t0h, t0l, t1h, t1l, c, top, keep, e, vp, vn, flat);
+    }
+    const uint32_t s0 = m - (flat & 0xFFFFu), s1 = m - (flat >> 16);
+    return (s0 < e + 1u ? s0 : e + 1u) | ((s1 < e + 1u ? s1 : e + 1u) << 16);
+}
+
+// Distance of one pair that passed the gate.  When every active lane has the
+// same threshold and length (always so for one read length and a uniform e),
+// the band's shifts and trip counts come from scalar registers.
 template <int W, int L>
+__device__ __forceinline__ uint32_t verify_pair(const PairIdx &p, const PairData<W> &d,
+                                                uint32_t m)
+{
+    uint32_t gh[W], gl[W], rh[W], rl[W];
+    pair_planes<W, L>(p, d, m, gh, gl, rh, rl);
+    const uint32_t e0 = __builtin_amdgcn_readfirstlane(p.e);
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(m);
+    if (__ballot(p.e != e0 || m != m0) == 0ull)
+        return e0 <= 15u ? band_distance<W, uint32_t>(rh, rl, gh, gl, m0, e0)
+                         : band_distance<W, B64>(rh, rl, gh, gl, m0, e0);
+    return p.e <= 15u ? band_distance<W, uint32_t>(rh, rl, gh, gl, m, p.e)
+                      : band_distance<W, B64>(rh, rl, gh, gl, m, p.e);
+}
+
+// Persistent over the list.  PAIRED (batches with one e <= 7, reads of up
+// to 8 words): a lane takes two list entries per step (t and t + stride);
+// when both pairs of every active lane pass the gate with the wave's one
+// length and e, the two share a 32-bit band word (band_distance2), otherwise
+// each is done on its own.  The paired loop holds two pairs' planes, so it
+// runs fewer waves; batches it cannot help take the one-pair loop.
+template <int W, int L, bool PAIRED>
 __global__ __launch_bounds__(256) void k_verify(FilterArgs a, const uint32_t *list,
                                                 const uint32_t *count, uint16_t *dist)
 {
     const uint32_t n = *count;
-    for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += gridDim.x * 256u) {
-        const uint32_t i = list[t];
-        const PairIdx p = load_idx(a, i);
-        PairData<W> d;
-        load_data<W>(a, p, d);
-        uint32_t m, out = GK_EST_NONE;
-        if (p.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p, d, m) == PAIR_OK) {
-            uint32_t gh[W], gl[W], rh[W], rl[W];
-            pair_planes<W, L>(p, d, m, gh, gl, rh, rl);
-            // When every active lane has the same threshold and length (always
-            // so for one read length and a uniform e), the band's shifts and
-            // trip counts come from scalar registers.
-            const uint32_t e0 = __builtin_amdgcn_readfirstlane(p.e);
-            const uint32_t m0 = __builtin_amdgcn_readfirstlane(m);
-            if (__ballot(p.e != e0 || m != m0) == 0ull)
-                out = e0 <= 15u ? band_distance<W, uint32_t>(rh, rl, gh, gl, m0, e0)
-                                : band_distance<W, B64>(rh, rl, gh, gl, m0, e0);
-            else
-                out = p.e <= 15u ? band_distance<W, uint32_t>(rh, rl, gh, gl, m, p.e)
-                                 : band_distance<W, B64>(rh, rl, gh, gl, m, p.e);
+    const uint32_t stride = gridDim.x * 256u;
+    if constexpr (PAIRED && W <= 8) {
+        for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += 2u * stride) {
+            const bool has1 = t + stride < n;
+            const uint32_t i0 = list[t];
+            const uint32_t i1 = has1 ? list[t + stride] : i0;
+            const PairIdx p0 = load_idx(a, i0);
+            const PairIdx p1 = load_idx(a, i1);
+            PairData<W> d0, d1;
+            load_data<W>(a, p0, d0);
+            load_data<W>(a, p1, d1);
+            uint32_t m0 = 0, m1 = 0;
+            const bool ok0 = p0.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p0, d0, m0) == PAIR_OK;
+            const bool ok1 = p1.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p1, d1, m1) == PAIR_OK;
+            const uint32_t ew = __builtin_amdgcn_readfirstlane(p0.e);
+            const uint32_t mw = __builtin_amdgcn_readfirstlane(m0);
+            uint32_t out0 = GK_EST_NONE, out1 = GK_EST_NONE;
+            const bool same = ok0 && ok1 && p0.e == ew && p1.e == ew && m0 == mw && m1 == mw;
+            if (ew <= 7u && __ballot(!same) == 0ull) {
+                uint32_t gh0[W], gl0[W], rh0[W], rl0[W], gh1[W], gl1[W], rh1[W], rl1[W];
+                pair_planes<W, L>(p0, d0, mw, gh0, gl0, rh0, rl0);
+                pair_planes<W, L>(p1, d1, mw, gh1, gl1, rh1, rl1);
+                const uint32_t two =
+                    band_distance2<W>(rh0, rl0, gh0, gl0, rh1, rl1, gh1, gl1, mw, ew);
+                out0 = two & 0xFFFFu;
+                out1 = two >> 16;
+            } else {
+                if (ok0)
+                    out0 = verify_pair<W, L>(p0, d0, m0);
+                if (ok1)
+                    out1 = verify_pair<W, L>(p1, d1, m1);
+            }
+            dist[i0] = (uint16_t)out0;
+            if (has1)
+                dist[i1] = (uint16_t)out1;
         }
-        dist[i] = (uint16_t)out;
+    } else {
+        for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += stride) {
+            const uint32_t i = list[t];
+            const PairIdx p = load_idx(a, i);
+            PairData<W> d;
+            load_data<W>(a, p, d);
+            uint32_t m, out = GK_EST_NONE;
+            if (p.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p, d, m) == PAIR_OK)
+                out = verify_pair<W, L>(p, d, m);
+            dist[i] = (uint16_t)out;
+        }
     }
 }
 
@@ -305,18 +426,33 @@ __global__ __launch_bounds__(256) void k_select_write(const uint8_t *accept, uin
         list[base + t] = stage[t];
 }
 
-template <int W, int L>
-hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, uint32_t *list,
-                     uint32_t *groups_buf, uint32_t *count, int cus, hipStream_t s)
+// Resident 256-lane workgroups per CU of one k_verify instantiation.
+template <int W, int L, bool PAIRED>
+hipError_t verify_blocks_per_cu(int &out)
 {
     static int per_cu = -1;
     if (per_cu < 0) {
         int v = 0;
-        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_verify<W, L>, 256, 0);
+        hipError_t e =
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_verify<W, L, PAIRED>, 256, 0);
         if (e != hipSuccess)
             return e;
         per_cu = v > 0 ? v : 1;
     }
+    out = per_cu;
+    return hipSuccess;
+}
+
+template <int W, int L>
+hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, uint32_t *list,
+                     uint32_t *groups_buf, uint32_t *count, int cus, hipStream_t s)
+{
+    const bool paired = W <= 8 && a.e_pair == nullptr && a.e_uniform <= 7u;
+    int per_cu = 1;
+    hipError_t oe = paired ? verify_blocks_per_cu<W, L, true>(per_cu)
+                           : verify_blocks_per_cu<W, L, false>(per_cu);
+    if (oe != hipSuccess)
+        return oe;
     const uint64_t CHUNK = 1ull << 30;
     for (uint64_t first = 0; first < a.n_pairs; first += CHUNK) {
         FilterArgs c = a;
@@ -347,8 +483,12 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
             hipLaunchKernelGGL(k_select_write<false>, dim3(groups), dim3(256), 0, s, acc,
                                (uint32_t)n, groups_buf, list);
         const uint64_t vb = want < (uint64_t)cus * per_cu ? want : (uint64_t)cus * per_cu;
-        hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vb), dim3(256), 0, s, c, list, count,
-                           out);
+        if (paired)
+            hipLaunchKernelGGL((k_verify<W, L, true>), dim3((uint32_t)vb), dim3(256), 0, s, c,
+                               list, count, out);
+        else
+            hipLaunchKernelGGL((k_verify<W, L, false>), dim3((uint32_t)vb), dim3(256), 0, s, c,
+                               list, count, out);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;

@@ -49,10 +49,12 @@ def edited_pairs(rng, ref, n, max_len=300, max_e=31, min_len=1):
     return reads, off, np.arange(n, dtype=np.uint32), np.array(pos, np.uint32), e
 
 
-def verify(ctx, reads, off, pr, pos, e, max_len, accept=None, layout=0):
+def verify(ctx, reads, off, pr, pos, e, max_len, accept=None, layout=0, e_uniform=None):
+    """e: per-pair thresholds, or None with e_uniform for the whole batch."""
     dr = device.encode_reads(ctx, reads, off, max_len=max_len, layout=layout)
     dp = device.upload_pairs(pr, pos, e)
-    b = device.batch_for(dr, dp, max_read_len=max_len)
+    b = device.batch_for(dr, dp, max_read_len=max_len,
+                         e_uniform=e_uniform if e_uniform is not None else 0)
     dist = torch.empty(len(pos), dtype=torch.int16, device="cuda")
     acc = None if accept is None else torch.from_numpy(accept).cuda()
     gk.gk_verify(ctx, b, acc, dist, None)
@@ -96,22 +98,27 @@ def test_verify_thresholds_and_lengths(gkctx):
     assert np.array_equal(d, want)
 
 
-@pytest.mark.parametrize("m,e", [(100, 0), (100, 5), (37, 3), (100, 15), (150, 16),
-                                 (250, 25), (512, 31), (300, 20)])
+@pytest.mark.parametrize("m,e", [(100, 0), (100, 5), (37, 3), (100, 7), (256, 7), (250, 6),
+                                 (100, 15), (150, 16), (250, 25), (512, 31), (300, 20)])
 def test_verify_uniform_waves(gkctx, m, e):
     """One length and one threshold for the whole batch: every wave takes the
-    path whose band shifts and trip counts are scalar (both band widths)."""
+    path whose band shifts and trip counts are scalar (both band widths).
+    Given as a per-pair array the pairs run one per lane; given as the batch's
+    uniform e (<= 7, up to 256 bases) two pairs share a band word."""
     rng = np.random.default_rng(1000 + m + e)
     ref = gen.c0_reference()
     gk.gk_load_reference(gkctx, ref)
-    reads, off, pr, pos, _ = edited_pairs(rng, ref, 3000, max_len=m, min_len=m)
+    reads, off, pr, pos, _ = edited_pairs(rng, ref, 3001, max_len=m, min_len=m)
     ev = np.full(len(pos), e, np.uint8)
-    say(f"case: verify uniform m={m} e={e}")
-    d = verify(gkctx, reads, off, pr, pos, ev, m)
     want = oracle_dist(ref, reads, off, pr, pos, ev)
-    bad = np.nonzero(d != want)[0]
-    assert len(bad) == 0, f"{len(bad)} differ; first {bad[0]}: gpu {d[bad[0]]} oracle {want[bad[0]]}"
-    assert np.any(d <= e) and np.any(d == e + 1)
+    for form in ("per-pair", "uniform"):
+        say(f"case: verify uniform m={m} e={e} ({form} e)")
+        d = (verify(gkctx, reads, off, pr, pos, ev, m) if form == "per-pair" else
+             verify(gkctx, reads, off, pr, pos, None, m, e_uniform=e))
+        bad = np.nonzero(d != want)[0]
+        assert len(bad) == 0, (f"{form}: {len(bad)} differ; first {bad[0]}: gpu {d[bad[0]]} "
+                               f"oracle {want[bad[0]]}")
+    assert np.any(want <= e) and np.any(want == e + 1)
 
 
 def test_verify_after_filter_and_status(gkctx):
