@@ -99,12 +99,14 @@ def test_verify_thresholds_and_lengths(gkctx):
 
 
 @pytest.mark.parametrize("m,e", [(100, 0), (100, 5), (37, 3), (100, 7), (256, 7), (250, 6),
-                                 (100, 15), (150, 16), (250, 25), (512, 31), (300, 20)])
+                                 (400, 6), (100, 15), (150, 16), (250, 25), (512, 31),
+                                 (300, 20)])
 def test_verify_uniform_waves(gkctx, m, e):
     """One length and one threshold for the whole batch: every wave takes the
     path whose band shifts and trip counts are scalar (both band widths).
     Given as a per-pair array the pairs run one per lane; given as the batch's
-    uniform e (<= 7, up to 256 bases) two pairs share a band word."""
+    uniform e (<= 7, up to 256 bases) two pairs share a band word; longer
+    reads with a uniform e <= 7 take the one-pair loop."""
     rng = np.random.default_rng(1000 + m + e)
     ref = gen.c0_reference()
     gk.gk_load_reference(gkctx, ref)
