@@ -63,6 +63,27 @@ def row(label, ref, ps, e, threads):
             f"{fr0} ({rate(fr0, nw)}) | {fah} ({rate(fah, nb)}) | {frh} ({rate(frh, nw)}) |")
 
 
+class _Pooled:
+    """Several pair sets as one: reads concatenated, pair_read re-based."""
+
+    def __init__(self, reads, read_off, pair_read, cand_pos):
+        self.reads, self.read_off = reads, read_off
+        self.pair_read, self.cand_pos = pair_read, cand_pos
+        self.n_pairs = len(cand_pos)
+
+
+def concat_sets(parts):
+    reads = np.concatenate([p.reads for p in parts])
+    offs, prs, base_r, base_b = [np.zeros(1, np.uint64)], [], 0, 0
+    for p in parts:
+        offs.append(p.read_off[1:].astype(np.uint64) + np.uint64(base_b))
+        prs.append(p.pair_read.astype(np.int64) + base_r)
+        base_r += len(p.read_off) - 1
+        base_b += int(p.read_off[-1])
+    return _Pooled(reads, np.concatenate(offs), np.concatenate(prs).astype(np.uint32),
+                   np.concatenate([p.cand_pos for p in parts]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--sample", type=int, default=1 << 18)
@@ -88,6 +109,21 @@ def main():
             print(row(f"config 2 ({m} bp), e={e}", ref, ps, e, th), flush=True)
     ps = gen.c3_pairs(ref, n_pairs=n)
     print(row("config 3 (64-300 bp), e per pair", ref, ps, ps.e, th), flush=True)
+    del ref, ps
+    # config 4: the served pool's first 16 requests (each its own length and
+    # e) over the 3.1 Gbp reference, at most n/32 seeded pairs of each
+    ref4 = gen.c4_reference()
+    rng = np.random.default_rng(4004)
+    parts = []
+    for k in range(16):
+        r = gen.c4_request(ref4, k)
+        keep = np.sort(rng.choice(r.n_pairs, size=min(r.n_pairs, n // 32), replace=False))
+        parts.append((_Pooled(r.reads, r.read_off, r.pair_read[keep], r.cand_pos[keep]),
+                      r.meta["e"]))
+    print(row("config 4 (100-250 bp, 16 requests), e per request", ref4,
+              concat_sets([p for p, _ in parts]),
+              np.concatenate([np.full(p.n_pairs, e, np.uint8) for p, e in parts]), th),
+          flush=True)
     print(f"\n{time.time() - t0:.0f} s on {th} threads, sample {n} pairs per row "
           f"(config 2: {n // 2})", file=sys.stderr)
 
