@@ -303,6 +303,15 @@ int gk_verify(gk_ctx *ctx, const gk_batch *batch, const uint8_t *accept, uint16_
 #define GK_OPT_MIXED_GRAPH          6  /* gk_filter_mixed: 1 (default)
                                             replays a captured hipGraph, 0
                                             launches directly               */
+#define GK_OPT_HOST_ENCODE_THREADS  7  /* gk_filter_host with ASCII reads:
+                                            0 (default) copies the text and
+                                            encodes it on the GPU; 1..64
+                                            encodes it into 2-bit words on
+                                            that many host threads, chunk by
+                                            chunk while the previous chunk is
+                                            copied and filtered, so a quarter
+                                            of the bytes cross the bus.  Same
+                                            results either way.             */
 
 /* Set / get a tuning option.  GK_EINVAL for an unknown option or a value out
    of range. */

@@ -618,6 +618,11 @@ int gk_set_option(gk_ctx *ctx, int option, int64_t value)
             return fail(ctx, GK_EINVAL, "gk_set_option: graph must be 0 or 1");
         ctx->use_graph = (uint32_t)value;
         return GK_OK;
+    case GK_OPT_HOST_ENCODE_THREADS:
+        if (value < 0 || value > 64)
+            return fail(ctx, GK_EINVAL, "gk_set_option: host encode threads must be 0..64");
+        ctx->host_encode_threads = (uint32_t)value;
+        return GK_OK;
     default:
         return fail(ctx, GK_EINVAL, "gk_set_option: unknown option");
     }
@@ -645,6 +650,9 @@ int gk_get_option(const gk_ctx *ctx, int option, int64_t *value)
         return GK_OK;
     case GK_OPT_MIXED_GRAPH:
         *value = ctx->use_graph;
+        return GK_OK;
+    case GK_OPT_HOST_ENCODE_THREADS:
+        *value = ctx->host_encode_threads;
         return GK_OK;
     default:
         return GK_EINVAL;

@@ -120,6 +120,14 @@ void gk_detail_free_host_pipe(gk_ctx *ctx)
         (void)hipEventDestroy(ev);
     h.ev_in.clear();
     h.ev_comp.clear();
+    for (uint8_t *&st : h.stage) {
+        if (st)
+            (void)hipHostFree(st);
+        st = nullptr;
+    }
+    h.stage_cap = 0;
+    h.pool.reset();
+    h.pool_threads = 0;
     for (hipStream_t *s : {&h.s_in, &h.s_comp, &h.s_out}) {
         if (*s)
             (void)hipStreamDestroy(*s);
@@ -170,9 +178,13 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
     const uint64_t nr = b->n_reads, np = b->n_pairs;
     const uint32_t pitch = (uint32_t)std::max<uint64_t>(64, (nr + 63) / 64 * 64);
     const uint32_t rows = (b->max_read_len + 15) / 16;
-    // ASCII text, or the host-encoded rows staged in the same buffer.
-    const uint64_t bytes = host_encoded ? nr * rows * sizeof(uint32_t)
-                                        : (nr ? b->read_off[nr] : 0);
+    // ASCII reads encoded here on host threads (GK_OPT_HOST_ENCODE_THREADS):
+    // 2-bit rows cross the bus, as for reads the caller encoded.
+    const bool encode_here = !host_encoded && ctx->host_encode_threads > 0 && nr > 0;
+    const bool rows_in = host_encoded || encode_here;
+    const uint64_t text_bytes = (!host_encoded && nr) ? b->read_off[nr] : 0;
+    // ASCII text, or 2-bit rows staged in the same buffer.
+    const uint64_t bytes = rows_in ? nr * rows * sizeof(uint32_t) : text_bytes;
     const bool identity = b->pair_read == nullptr;
 
     // Chunks of at least 2^20 pairs, at most 16 of them.
@@ -184,6 +196,31 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
     hipError_t e = ensure_buffers(h, bytes, nr, (uint64_t)rows * pitch, np, K);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "device buffers");
+    // Two pinned staging buffers, each one read chunk of rows, lengths and
+    // unknown-base flags; chunk j uses buffer j % 2 once chunk j - 2's copy
+    // from it is done.
+    const uint64_t stage_rows_bytes = R * rows * sizeof(uint32_t);
+    const uint64_t stage_bytes = stage_rows_bytes + R * sizeof(uint16_t) + R;
+    if (encode_here) {
+        if (stage_bytes > h.stage_cap) {
+            for (uint8_t *&st : h.stage) {
+                if (st)
+                    (void)hipHostFree(st);
+                st = nullptr;
+            }
+            h.stage_cap = 0;
+            for (uint8_t *&st : h.stage)
+                if ((e = hipHostMalloc((void **)&st, stage_bytes, hipHostMallocDefault)) !=
+                    hipSuccess)
+                    return hip_fail(ctx, e, "pinned staging");
+            h.stage_cap = stage_bytes;
+        }
+        if (h.pool_threads != ctx->host_encode_threads) {
+            h.pool.reset();
+            h.pool.reset(new gkd::HostEncodePool(ctx->host_encode_threads));
+            h.pool_threads = ctx->host_encode_threads;
+        }
+    }
 
     std::vector<uint32_t> need(K, 0);   // last read chunk each pair chunk needs
     bool bad_offsets = false;
@@ -193,8 +230,37 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         const uint64_t r0 = std::min<uint64_t>(nr, (uint64_t)j * R);
         const uint64_t r1 = std::min<uint64_t>(nr, r0 + R);
         uint32_t *rows_dev =
-            host_encoded ? reinterpret_cast<uint32_t *>(h.ascii) + r0 * rows : nullptr;
-        if (r1 > r0 && host_encoded) {
+            rows_in ? reinterpret_cast<uint32_t *>(h.ascii) + r0 * rows : nullptr;
+        if (r1 > r0 && encode_here) {
+            for (uint64_t r = r0; r < r1 && !bad_offsets; ++r)
+                bad_offsets = b->read_off[r + 1] < b->read_off[r];
+            bad_offsets = bad_offsets || b->read_off[r1] > text_bytes;
+            if (bad_offsets)
+                break;
+            if (j >= 2)
+                e = hipEventSynchronize(h.ev_in[j - 2]);
+            uint8_t *st = h.stage[j & 1u];
+            uint32_t *rows_h = reinterpret_cast<uint32_t *>(st);
+            uint16_t *len_h = reinterpret_cast<uint16_t *>(st + stage_rows_bytes);
+            uint8_t *has_n_h = st + stage_rows_bytes + R * sizeof(uint16_t);
+            if (e == hipSuccess) {
+                const uint64_t cnt = r1 - r0;
+                h.pool->run([&](unsigned i, unsigned n) {
+                    const uint64_t a = r0 + cnt * i / n, z = r0 + cnt * (i + 1) / n;
+                    gkd::host_encode_rows(b->ascii, text_bytes, b->read_off, a, z, rows,
+                                          rows_h + (a - r0) * rows, len_h + (a - r0),
+                                          has_n_h + (a - r0));
+                });
+                e = hipMemcpyAsync(rows_dev, rows_h, cnt * rows * sizeof(uint32_t),
+                                   hipMemcpyHostToDevice, h.s_in);
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(h.len + r0, len_h, (r1 - r0) * sizeof(uint16_t),
+                                   hipMemcpyHostToDevice, h.s_in);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(h.has_n + r0, has_n_h, r1 - r0, hipMemcpyHostToDevice,
+                                   h.s_in);
+        } else if (r1 > r0 && host_encoded) {
             e = hipMemcpyAsync(rows_dev, b->packed + r0 * rows,
                                (r1 - r0) * rows * sizeof(uint32_t), hipMemcpyHostToDevice,
                                h.s_in);
@@ -248,7 +314,7 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         if (e == hipSuccess)
             e = hipStreamWaitEvent(h.s_comp, h.ev_in[j], 0);
         if (e == hipSuccess && r1 > r0)
-            e = host_encoded
+            e = rows_in
                     ? gkd::launch_transpose_reads(rows_dev, (uint32_t)(r1 - r0), rows, pitch,
                                                   h.packed + r0, h.s_comp)
                     : gkd::launch_encode_reads(h.ascii, h.off + r0, (uint32_t)(r1 - r0), pitch,
@@ -265,7 +331,7 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
             fb.pitch = pitch;
             fb.max_read_len = b->max_read_len;
             fb.e_uniform = b->e_uniform;
-            fb.read_layout = host_encoded ? b->packed_layout : GK_READS_SPLIT;
+            fb.read_layout = host_encoded ? b->packed_layout : GK_READS_SPLIT;   // encode_here: split
             fb.flags = b->flags;
             fb.n_pairs = q1 - q0;
             fb.cand_pos = h.cand_pos + q0;

@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "gk.h"
 #include "gk_args.h"
+#include "gk_host_encode.h"
 
 // Tuning of the mixed-batch launch (never changes results).
 struct MixedConfig {
@@ -36,6 +38,10 @@ struct HostPipe {
     uint16_t *est = nullptr;
     uint64_t pair_cap = 0;       // pairs
     std::vector<hipEvent_t> ev_in, ev_comp;
+    uint8_t *stage[2] = {nullptr, nullptr};   // pinned: host-encoded read chunks
+    uint64_t stage_cap = 0;      // bytes of each
+    std::unique_ptr<gkd::HostEncodePool> pool;  // host encoding threads
+    unsigned pool_threads = 0;
 };
 
 struct gk_ctx {
@@ -54,6 +60,7 @@ struct gk_ctx {
     // mixed-batch launch
     MixedConfig mixed;
     uint32_t use_graph = 1;                   // GK_OPT_MIXED_GRAPH
+    uint32_t host_encode_threads = 0;         // GK_OPT_HOST_ENCODE_THREADS
     uint32_t *d_mixed_counters = nullptr;     // [tile counter, residual count]
     uint32_t *d_resid = nullptr;              // residual pair list
     uint64_t resid_cap = 0;

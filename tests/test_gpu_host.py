@@ -9,6 +9,16 @@ from gpu_cases import assert_same, concat_reads, pack_reads_rows, run_gpu, run_o
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(params=[0, 4], ids=["gpu-encode", "host-encode"])
+def encode_threads(gkctx, request):
+    """ASCII reads encoded on the GPU (0) or on 4 host threads
+    (GK_OPT_HOST_ENCODE_THREADS): the same results either way."""
+    from paper_2103_14978_amd import gk
+    gk.gk_set_option(gkctx, gk.GK_OPT_HOST_ENCODE_THREADS, request.param)
+    yield request.param
+    gk.gk_set_option(gkctx, gk.GK_OPT_HOST_ENCODE_THREADS, 0)
+
+
 def host_filter(ctx, ps, *, max_read_len, e=None, e_uniform=0, identity=False, pinned=False):
     from paper_2103_14978_amd import gk
     n = ps.n_pairs
@@ -36,7 +46,7 @@ def host_filter(ctx, ps, *, max_read_len, e=None, e_uniform=0, identity=False, p
     return acc, est
 
 
-def test_host_config0(gkctx):
+def test_host_config0(gkctx, encode_threads):
     from paper_2103_14978_amd import gk
     ref = gen.c0_reference()
     gk.gk_load_reference(gkctx, ref)
@@ -49,7 +59,7 @@ def test_host_config0(gkctx):
 
 
 @pytest.mark.parametrize("pinned", [False, True])
-def test_host_multichunk_shuffled(gkctx, pinned):
+def test_host_multichunk_shuffled(gkctx, pinned, encode_threads):
     """3M pairs (three chunks) of 150 bp reads with several candidates each,
     pairs shuffled so that a chunk's pairs need reads of later chunks; per
     pair e.  Same results as the oracle and as gk_filter on device buffers."""
@@ -61,8 +71,12 @@ def test_host_multichunk_shuffled(gkctx, pinned):
     perm = rng.permutation(ps.n_pairs)
     ps.pair_read = ps.pair_read[perm].copy()
     ps.cand_pos = ps.cand_pos[perm].copy()
+    ps.reads = ps.reads.copy()
+    ps.reads[np.arange(300, len(ps.reads), 7001)] = ord("N")        # unknown bases
+    low = np.arange(10, len(ps.reads), 997)
+    ps.reads[low] = np.char.lower(ps.reads[low].view("S1")).view(np.uint8)
     e = rng.integers(0, 16, ps.n_pairs).astype(np.uint8)
-    say(f"case: host multichunk pinned={pinned} pairs={ps.n_pairs}")
+    say(f"case: host multichunk pinned={pinned} threads={encode_threads} pairs={ps.n_pairs}")
     a, s = host_filter(gkctx, ps, max_read_len=150, e=e, pinned=pinned)
     a2, s2, _ = run_gpu(gkctx, ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, e,
                         max_read_len=150, load_ref=False)
@@ -72,13 +86,13 @@ def test_host_multichunk_shuffled(gkctx, pinned):
     assert_same(a[idx], s[idx], ra, rs, "host vs oracle")
 
 
-def test_host_identity_multichunk(gkctx):
+def test_host_identity_multichunk(gkctx, encode_threads):
     """2^21 + 333 pairs, one per read (the ragged last chunk), e uniform."""
     from paper_2103_14978_amd import gk
     ref = gen.c1_reference()
     gk.gk_load_reference(gkctx, ref)
     ps = gen.c1_pairs(ref, 5, n_pairs=(1 << 21) + 333)
-    say("case: host identity multichunk")
+    say(f"case: host identity multichunk threads={encode_threads}")
     a, s = host_filter(gkctx, ps, max_read_len=100, e_uniform=5, identity=True, pinned=True)
     a2, s2, _ = run_gpu(gkctx, ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, 5,
                         max_read_len=100, load_ref=False, identity_as_null=True)
@@ -88,7 +102,7 @@ def test_host_identity_multichunk(gkctx):
     assert_same(a[idx], s[idx], ra, rs, "host identity vs oracle")
 
 
-def test_host_status_and_errors(gkctx):
+def test_host_status_and_errors(gkctx, encode_threads):
     """Unknown bases, over-long reads and bad read indices give per-pair
     codes; bad offsets and buffers are call errors; no reference is ENOREF."""
     from paper_2103_14978_amd import gk
