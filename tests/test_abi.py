@@ -94,12 +94,16 @@ def test_errors(gkctx):
             gk.gk_filter(ctx2, bad)
         assert ei.value.status == gk.GK_EINVAL
         for opt, val in ((gk.GK_OPT_PAIRS_PER_LANE, -1), (gk.GK_OPT_PAIRS_PER_LANE, 65537),
-                         (999, 0)):
+                         (gk.GK_OPT_HOST_ENCODE_THREADS, -1),
+                         (gk.GK_OPT_HOST_ENCODE_THREADS, 65), (999, 0)):
             with pytest.raises(gk.GkError) as ei:
                 gk.gk_set_option(ctx2, opt, val)
             assert ei.value.status == gk.GK_EINVAL
         gk.gk_set_option(ctx2, gk.GK_OPT_PAIRS_PER_LANE, 5)
         assert gk.gk_get_option(ctx2, gk.GK_OPT_PAIRS_PER_LANE) == 5
+        assert gk.gk_get_option(ctx2, gk.GK_OPT_HOST_ENCODE_THREADS) == 0
+        gk.gk_set_option(ctx2, gk.GK_OPT_HOST_ENCODE_THREADS, 64)
+        assert gk.gk_get_option(ctx2, gk.GK_OPT_HOST_ENCODE_THREADS) == 64
         torch.cuda.synchronize()
     finally:
         gk.gk_destroy(ctx2)
