@@ -229,12 +229,16 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
                 sorted[atomicAdd(&s.hist[key], 1u)] = (uint16_t)j;
         }
 
-        // 4. chunks: runs of one W, 64 * ppl pairs at most
+        // 4. chunks: runs of one W, 64 * ppl pairs at most.  A W's pairs are
+        //    in ascending k_max, so its one partial chunk is put first, on the
+        //    pairs with the fewest shifts: its idle lanes then wait through
+        //    the shortest loop.
         if (tid < 64) {
             const uint32_t ch = 64u * PPL;
             const uint32_t w0 = tid < 16 ? s.wstart[tid] : 0u;
             const uint32_t cnt = tid < 16 ? s.wstart[tid + 1] - w0 : 0u;
             const uint32_t nch = (cnt + ch - 1) / ch;
+            const uint32_t lead = cnt % ch == 0u ? ch : cnt % ch;   // size of chunk 0
             uint32_t incl = nch;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -244,9 +248,8 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
             }
             const uint32_t first = incl - nch;
             for (uint32_t c = 0; c < nch; ++c) {
-                chunk_start[first + c] = w0 + c * ch;
-                const uint32_t left = cnt - c * ch;
-                chunk_info[first + c] = (left < ch ? left : ch) | ((tid + 1u) << 16);
+                chunk_start[first + c] = w0 + (c == 0u ? 0u : lead + (c - 1u) * ch);
+                chunk_info[first + c] = (c == 0u ? lead : ch) | ((tid + 1u) << 16);
             }
             if (tid == 63) {
                 s.n_chunks = incl;
@@ -255,7 +258,8 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
         }
         __syncthreads();
 
-        // 5. waves take chunks
+        // 5. waves take chunks, the heaviest (largest W and k_max, at the
+        //    end of the list) first, so the tile ends on short chunks
         const uint32_t n_chunks = s.n_chunks;
         while (true) {
             uint32_t c = 0;
@@ -264,6 +268,7 @@ __global__ __launch_bounds__(256) void k_mixed(FilterArgs a0, MixedArgs x)
             c = __shfl(c, 0, 64);
             if (c >= n_chunks)
                 break;
+            c = n_chunks - 1u - c;
             const uint32_t start = chunk_start[c];
             const uint32_t info = chunk_info[c];
             const uint32_t cnt = info & 0xFFFFu;
