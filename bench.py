@@ -455,6 +455,16 @@ def main() -> int:
         dt1 = time.perf_counter() - t
         cpu["one_core"] = {"value": round(one / dt1, 1), "unit": "pairs/s",
                            "sample": f"first {one} pairs, 1 thread, {dt1:.2f}s wall"}
+        # Config 0 in full on one core (10,000 pairs of 100 bp, e = 2).
+        ref0 = gen.c0_reference()
+        ps0 = gen.c0_pairs(ref0)
+        t = time.perf_counter()
+        oracle.filter_batch(ps0.reads, ps0.read_off, ref0, ps0.pair_read, ps0.cand_pos, 2,
+                            n_threads=1)
+        dt0 = time.perf_counter() - t
+        cpu["one_core_config0"] = {"value": round(ps0.n_pairs / dt0, 1), "unit": "pairs/s",
+                                   "sample": f"config 0 in full ({ps0.n_pairs} pairs, e=2), "
+                                             f"1 thread, {dt0 * 1e3:.1f} ms wall"}
         cpu["host_cpu"] = host_cpu_model()
 
     out = {
