@@ -417,6 +417,7 @@ def main() -> int:
     roofline = {"bound": "alu", "kernel": kname + ">", "achieved": round(achieved_tops, 3),
                 "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
                 "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                "traffic_GBs": (round(traffic / k_avg_s / 1e9, 1) if traffic else None),
                 "ops_per_pair": ops_per_pair(m, e), "kernel_ms": round(k_avg_s * 1e3, 4),
                 "kernel_ms_min": round(float(np.min(kernel_ms)), 4),
                 "kernel_ms_median": round(float(np.median(kernel_ms)), 4),
@@ -751,6 +752,7 @@ def bench_mixed(args, log) -> int:
         "roofline": {"bound": "alu", "kernel": "k_mixed<10>", "achieved": round(achieved, 3),
                      "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
                      "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": mtraffic,
+                     "traffic_GBs": (round(mtraffic / k_m / 1e9, 1) if mtraffic else None),
                      "ops_per_pair_mean": round(ops / n_pairs, 1),
                      "kernel_ms": round(k_m * 1e3, 4), "kernel_source_hash": mhash},
         "parity": parity,
