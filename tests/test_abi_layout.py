@@ -63,3 +63,23 @@ def test_constants_match_header():
         m = re.search(rf"#define\s+{name}\s+(\w+)", hdr)
         assert m, name
         assert int(m.group(1).rstrip("uU").rstrip("uU"), 0) == getattr(gk, name), name
+
+
+def test_readme_c_example_compiles(tmp_path):
+    """The C example in README.md compiles against include/gk.h."""
+    import re
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not found")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "README.md")).read()
+    blocks = re.findall(r"```c\n(.*?)```", text, re.S)
+    assert blocks, "no C example in README.md"
+    src = tmp_path / "example.c"
+    src.write_text(blocks[0])
+    r = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-I",
+                        os.path.join(root, "include"), "-c", str(src), "-o",
+                        str(tmp_path / "example.o")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
