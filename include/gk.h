@@ -271,9 +271,10 @@ int gk_filter_host(gk_ctx *ctx, const gk_host_batch *batch);
  * exactly when the pair lies within e_i edits; GK_EST_NONE for pairs not
  * verified, for pairs gk_filter marks GK_UNDEFINED or GK_INVALID, and for
  * e_i > GK_VERIFY_MAX_E.
- * Asynchronous on stream.  Uses context-owned scratch (a pair list of up to
- * 2^30 entries, allocated on first use): calls on one context must not
- * overlap on different streams.  Errors as gk_filter, plus GK_EINVAL for a
+ * Asynchronous on stream.  Uses context-owned scratch (two pair lists of up
+ * to 2^30 entries each, 8 bytes per pair of the largest batch so far plus a
+ * word per 4096 pairs, allocated on first use and grown as needed): calls on
+ * one context must not overlap on different streams.  Errors as gk_filter, plus GK_EINVAL for a
  * NULL dist.
  */
 #define GK_VERIFY_MAX_E 31u

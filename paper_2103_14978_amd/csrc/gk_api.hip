@@ -496,8 +496,9 @@ int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *d
     DeviceGuard g(ctx->device);
     if (!g.ok)
         return fail(ctx, GK_EDEVICE, "gk_verify: hipSetDevice failed");
-    // The pair list (one word per pair of a chunk of up to 2^30) followed by
-    // one word per 4096 of those pairs for the listing's per-workgroup counts.
+    // The pair list (one word per pair of a chunk of up to 2^30), one word
+    // per 4096 of those pairs for the listing's per-workgroup counts, and the
+    // list of pairs the paired verify kernel leaves to the one-pair kernel.
     const uint64_t need = std::min<uint64_t>(b->n_pairs, 1ull << 30);
     if (need > ctx->verify_cap) {
         if (ctx->d_verify_list)
@@ -505,20 +506,22 @@ int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *d
         ctx->d_verify_list = nullptr;
         ctx->verify_cap = 0;
         hipError_t e = hipMalloc(&ctx->d_verify_list,
-                                 (need + (need + 4095) / 4096) * sizeof(uint32_t));
+                                 (2 * need + (need + 4095) / 4096) * sizeof(uint32_t));
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_verify: hipMalloc list");
         ctx->verify_cap = need;
     }
     if (!ctx->d_verify_count) {
-        hipError_t e = hipMalloc(&ctx->d_verify_count, sizeof(uint32_t));
+        hipError_t e = hipMalloc(&ctx->d_verify_count, 2 * sizeof(uint32_t));
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_verify: hipMalloc count");
     }
     const uint32_t words = (b->max_read_len + 31) / 32;
-    hipError_t e = gkd::launch_verify(a, accept, dist, ctx->d_verify_list,
-                                      ctx->d_verify_list + ctx->verify_cap, ctx->d_verify_count,
-                                      words, b->read_layout, ctx->cu_count, (hipStream_t)stream);
+    uint32_t *groups = ctx->d_verify_list + ctx->verify_cap;
+    uint32_t *deferred = groups + (ctx->verify_cap + 4095) / 4096;
+    hipError_t e = gkd::launch_verify(a, accept, dist, ctx->d_verify_list, groups, deferred,
+                                      ctx->d_verify_count, words, b->read_layout,
+                                      ctx->cu_count, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "gk_verify: launch");
     return GK_OK;

@@ -69,7 +69,9 @@ struct gk_ctx {
     std::vector<uint8_t> graph_key;
     HostPipe host;                            // gk_filter_host
     uint32_t *d_verify_list = nullptr;        // gk_verify: selected pairs (verify_cap
-                                              // words), then per-workgroup counts
+                                              // words), per-workgroup counts, deferred
+                                              // pairs (verify_cap words)
+    // d_verify_count: [0] selected pairs, [1] deferred pairs
     uint32_t *d_verify_count = nullptr;
     uint64_t verify_cap = 0;
 };

@@ -8,10 +8,11 @@ namespace gkd {
 // dist[i] = min(edit distance, e_i + 1) for the pairs with accept[i] ==
 // GK_ACCEPT (every pair when accept is NULL); GK_EST_NONE for the others and
 // for pairs that cannot be compared or have e_i > GK_VERIFY_MAX_E.  list,
-// groups and count are scratch: min(n_pairs, 2^30) words, one word per 4096
-// of those pairs (rounded up) and one word.
+// groups, deferred and count are scratch: min(n_pairs, 2^30) words, one word
+// per 4096 of those pairs (rounded up), min(n_pairs, 2^30) words and two
+// words.
 hipError_t launch_verify(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
-                         uint32_t *list, uint32_t *groups, uint32_t *count, uint32_t words,
-                         uint32_t layout, int cus, hipStream_t s);
+                         uint32_t *list, uint32_t *groups, uint32_t *deferred, uint32_t *count,
+                         uint32_t words, uint32_t layout, int cus, hipStream_t s);
 
 }  // namespace gkd

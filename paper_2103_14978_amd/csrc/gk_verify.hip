@@ -234,63 +234,90 @@ __device__ __forceinline__ uint32_t verify_pair(const PairIdx &p, const PairData
                       : band_distance<W, B64>(rh, rl, gh, gl, m, p.e);
 }
 
-// Persistent over the list.  PAIRED (batches with one e <= 7, reads of up
-// to 8 words): a lane takes two list entries per step (t and t + stride);
-// when both pairs of every active lane pass the gate with the wave's one
-// length and e, the two share a 32-bit band word (band_distance2), otherwise
-// each is done on its own.  The paired loop holds two pairs' planes, so it
-// runs fewer waves; batches it cannot help take the one-pair loop.
-template <int W, int L, bool PAIRED>
+// Persistent over the list, one pair per lane.
+template <int W, int L>
 __global__ __launch_bounds__(256) void k_verify(FilterArgs a, const uint32_t *list,
                                                 const uint32_t *count, uint16_t *dist)
 {
     const uint32_t n = *count;
     const uint32_t stride = gridDim.x * 256u;
-    if constexpr (PAIRED && W <= 8) {
-        for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += 2u * stride) {
-            const bool has1 = t + stride < n;
-            const uint32_t i0 = list[t];
-            const uint32_t i1 = has1 ? list[t + stride] : i0;
-            const PairIdx p0 = load_idx(a, i0);
-            const PairIdx p1 = load_idx(a, i1);
-            PairData<W> d0, d1;
-            load_data<W>(a, p0, d0);
-            load_data<W>(a, p1, d1);
-            uint32_t m0 = 0, m1 = 0;
-            const bool ok0 = p0.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p0, d0, m0) == PAIR_OK;
-            const bool ok1 = p1.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p1, d1, m1) == PAIR_OK;
-            const uint32_t ew = __builtin_amdgcn_readfirstlane(p0.e);
-            const uint32_t mw = __builtin_amdgcn_readfirstlane(m0);
-            uint32_t out0 = GK_EST_NONE, out1 = GK_EST_NONE;
-            const bool same = ok0 && ok1 && p0.e == ew && p1.e == ew && m0 == mw && m1 == mw;
-            if (ew <= 7u && __ballot(!same) == 0ull) {
-                uint32_t gh0[W], gl0[W], rh0[W], rl0[W], gh1[W], gl1[W], rh1[W], rl1[W];
-                pair_planes<W, L>(p0, d0, mw, gh0, gl0, rh0, rl0);
-                pair_planes<W, L>(p1, d1, mw, gh1, gl1, rh1, rl1);
-                const uint32_t two =
-                    band_distance2<W>(rh0, rl0, gh0, gl0, rh1, rl1, gh1, gl1, mw, ew);
-                out0 = two & 0xFFFFu;
-                out1 = two >> 16;
-            } else {
-                if (ok0)
-                    out0 = verify_pair<W, L>(p0, d0, m0);
-                if (ok1)
-                    out1 = verify_pair<W, L>(p1, d1, m1);
-            }
-            dist[i0] = (uint16_t)out0;
-            if (has1)
-                dist[i1] = (uint16_t)out1;
+    for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += stride) {
+        const uint32_t i = list[t];
+        const PairIdx p = load_idx(a, i);
+        PairData<W> d;
+        load_data<W>(a, p, d);
+        uint32_t m, out = GK_EST_NONE;
+        if (p.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p, d, m) == PAIR_OK)
+            out = verify_pair<W, L>(p, d, m);
+        dist[i] = (uint16_t)out;
+    }
+}
+
+// Persistent over the list, two entries per lane per step (t and t + stride),
+// for batches with one e <= 7 and reads of up to 8 words.  When every pair of
+// the wave that passes the gate has the length and e of the wave's first such
+// pair, each lane's two pairs share a 32-bit band word (band_distance2); pairs
+// that fail the gate get GK_EST_NONE.  Otherwise the wave appends its pairs to
+// `deferred` (one atomic per wave) for k_verify to do one per lane.  Keeping
+// that fallback out of this kernel keeps its registers low (two pairs' planes
+// already fill most of them).
+template <int W, int L>
+__global__ __launch_bounds__(256) void k_verify_paired(FilterArgs a, const uint32_t *list,
+                                                       const uint32_t *count, uint16_t *dist,
+                                                       uint32_t *deferred,
+                                                       uint32_t *deferred_count)
+{
+    const uint32_t n = *count;
+    const uint32_t stride = gridDim.x * 256u;
+    const uint32_t lane = threadIdx.x & 63u;
+    for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += 2u * stride) {
+        const bool has1 = t + stride < n;
+        const uint32_t i0 = list[t];
+        const uint32_t i1 = has1 ? list[t + stride] : i0;
+        const PairIdx p0 = load_idx(a, i0);
+        const PairIdx p1 = load_idx(a, i1);
+        PairData<W> d0, d1;
+        load_data<W>(a, p0, d0);
+        load_data<W>(a, p1, d1);
+        uint32_t m0 = 0, m1 = 0;
+        const bool ok0 = p0.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p0, d0, m0) == PAIR_OK;
+        const bool ok1 = p1.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p1, d1, m1) == PAIR_OK;
+        // the wave's length and e: those of its first pair that passed the gate
+        const unsigned long long v0 = __ballot(ok0), v1 = __ballot(ok1);
+        uint32_t ew = 0, mw = 0;
+        if (v0) {
+            const int src = __builtin_ctzll(v0);
+            ew = (uint32_t)__builtin_amdgcn_readlane((int)p0.e, src);
+            mw = (uint32_t)__builtin_amdgcn_readlane((int)m0, src);
+        } else if (v1) {
+            const int src = __builtin_ctzll(v1);
+            ew = (uint32_t)__builtin_amdgcn_readlane((int)p1.e, src);
+            mw = (uint32_t)__builtin_amdgcn_readlane((int)m1, src);
         }
-    } else {
-        for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += stride) {
-            const uint32_t i = list[t];
-            const PairIdx p = load_idx(a, i);
-            PairData<W> d;
-            load_data<W>(a, p, d);
-            uint32_t m, out = GK_EST_NONE;
-            if (p.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p, d, m) == PAIR_OK)
-                out = verify_pair<W, L>(p, d, m);
-            dist[i] = (uint16_t)out;
+        const bool fits = (!ok0 || (p0.e == ew && m0 == mw)) && (!ok1 || (p1.e == ew && m1 == mw));
+        if ((v0 | v1) == 0ull) {
+            dist[i0] = (uint16_t)GK_EST_NONE;
+            if (has1)
+                dist[i1] = (uint16_t)GK_EST_NONE;
+        } else if (ew <= 7u && __ballot(!fits) == 0ull) {
+            uint32_t gh0[W], gl0[W], rh0[W], rl0[W], gh1[W], gl1[W], rh1[W], rl1[W];
+            pair_planes<W, L>(p0, d0, mw, gh0, gl0, rh0, rl0);
+            pair_planes<W, L>(p1, d1, mw, gh1, gl1, rh1, rl1);
+            const uint32_t two = band_distance2<W>(rh0, rl0, gh0, gl0, rh1, rl1, gh1, gl1, mw, ew);
+            dist[i0] = (uint16_t)(ok0 ? (two & 0xFFFFu) : GK_EST_NONE);
+            if (has1)
+                dist[i1] = (uint16_t)(ok1 ? (two >> 16) : GK_EST_NONE);
+        } else {
+            const unsigned long long act = __ballot(true), two = __ballot(has1);
+            const uint32_t n_act = (uint32_t)__popcll(act), n_two = (uint32_t)__popcll(two);
+            uint32_t base = 0;
+            if (lane == (uint32_t)__builtin_ctzll(act))
+                base = atomicAdd(deferred_count, n_act + n_two);
+            base = (uint32_t)__builtin_amdgcn_readlane((int)base, __builtin_ctzll(act));
+            const unsigned long long below = (1ull << lane) - 1ull;
+            deferred[base + (uint32_t)__popcll(act & below)] = i0;
+            if (has1)
+                deferred[base + n_act + (uint32_t)__popcll(two & below)] = i1;
         }
     }
 }
@@ -356,7 +383,7 @@ __global__ __launch_bounds__(256) void k_select_count(const uint8_t *accept, uin
 }
 
 // One workgroup of 1024 lanes: exclusive prefix sums of groups (<= 2^18)
-// counts in place, and the total into *count.
+// counts in place, the total into count[0] and 0 into count[1].
 __global__ __launch_bounds__(1024) void k_select_scan(uint32_t *group_count, uint32_t groups,
                                                       uint32_t *count)
 {
@@ -387,8 +414,10 @@ __global__ __launch_bounds__(1024) void k_select_scan(uint32_t *group_count, uin
         group_count[i] = run;
         run += v;
     }
-    if (threadIdx.x == 1023u)
-        *count = before + incl;
+    if (threadIdx.x == 1023u) {
+        count[0] = before + incl;
+        count[1] = 0u;               // k_verify_paired's deferred pairs
+    }
 }
 
 template <bool VEC>
@@ -426,15 +455,18 @@ __global__ __launch_bounds__(256) void k_select_write(const uint8_t *accept, uin
         list[base + t] = stage[t];
 }
 
-// Resident 256-lane workgroups per CU of one k_verify instantiation.
+// Resident 256-lane workgroups per CU of k_verify (PAIRED false) or
+// k_verify_paired (true).
 template <int W, int L, bool PAIRED>
 hipError_t verify_blocks_per_cu(int &out)
 {
     static int per_cu = -1;
     if (per_cu < 0) {
         int v = 0;
-        hipError_t e =
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, k_verify<W, L, PAIRED>, 256, 0);
+        hipError_t e = PAIRED ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                    &v, k_verify_paired<W, L>, 256, 0)
+                              : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                                    &v, k_verify<W, L>, 256, 0);
         if (e != hipSuccess)
             return e;
         per_cu = v > 0 ? v : 1;
@@ -445,12 +477,14 @@ hipError_t verify_blocks_per_cu(int &out)
 
 template <int W, int L>
 hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, uint32_t *list,
-                     uint32_t *groups_buf, uint32_t *count, int cus, hipStream_t s)
+                     uint32_t *groups_buf, uint32_t *deferred, uint32_t *count, int cus,
+                     hipStream_t s)
 {
     const bool paired = W <= 8 && a.e_pair == nullptr && a.e_uniform <= 7u;
-    int per_cu = 1;
-    hipError_t oe = paired ? verify_blocks_per_cu<W, L, true>(per_cu)
-                           : verify_blocks_per_cu<W, L, false>(per_cu);
+    int per_cu = 1, per_cu1 = 1;
+    hipError_t oe = verify_blocks_per_cu<W, L, false>(per_cu1);
+    if (oe == hipSuccess && paired)
+        oe = verify_blocks_per_cu<W, L, true>(per_cu);
     if (oe != hipSuccess)
         return oe;
     const uint64_t CHUNK = 1ull << 30;
@@ -482,13 +516,19 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
         else
             hipLaunchKernelGGL(k_select_write<false>, dim3(groups), dim3(256), 0, s, acc,
                                (uint32_t)n, groups_buf, list);
-        const uint64_t vb = want < (uint64_t)cus * per_cu ? want : (uint64_t)cus * per_cu;
-        if (paired)
-            hipLaunchKernelGGL((k_verify<W, L, true>), dim3((uint32_t)vb), dim3(256), 0, s, c,
-                               list, count, out);
-        else
-            hipLaunchKernelGGL((k_verify<W, L, false>), dim3((uint32_t)vb), dim3(256), 0, s, c,
-                               list, count, out);
+        const uint64_t vb1 = want < (uint64_t)cus * per_cu1 ? want : (uint64_t)cus * per_cu1;
+        if (paired) {
+            const uint64_t want2 = (n + 511) / 512;        // two pairs per lane
+            const uint64_t vb = want2 < (uint64_t)cus * per_cu ? want2 : (uint64_t)cus * per_cu;
+            hipLaunchKernelGGL((k_verify_paired<W, L>), dim3((uint32_t)vb), dim3(256), 0, s, c,
+                               list, count, out, deferred, count + 1);
+            // the waves it could not pair (count[1] entries, usually none)
+            hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vb1), dim3(256), 0, s, c,
+                               (const uint32_t *)deferred, (const uint32_t *)(count + 1), out);
+        } else {
+            hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vb1), dim3(256), 0, s, c, list,
+                               count, out);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -498,25 +538,26 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
 
 template <int L>
 hipError_t verify_l(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, uint32_t *list,
-                    uint32_t *groups_buf, uint32_t *count, uint32_t words, int cus, hipStream_t s)
+                    uint32_t *groups_buf, uint32_t *deferred, uint32_t *count, uint32_t words,
+                    int cus, hipStream_t s)
 {
     switch (words) {
-    case 1: return verify_wl<1, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 2: return verify_wl<2, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 3: return verify_wl<3, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 4: return verify_wl<4, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 5: return verify_wl<5, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 6: return verify_wl<6, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 7: return verify_wl<7, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 8: return verify_wl<8, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 9: return verify_wl<9, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 10: return verify_wl<10, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 11: return verify_wl<11, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 12: return verify_wl<12, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 13: return verify_wl<13, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 14: return verify_wl<14, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 15: return verify_wl<15, L>(a, accept, dist, list, groups_buf, count, cus, s);
-    case 16: return verify_wl<16, L>(a, accept, dist, list, groups_buf, count, cus, s);
+    case 1: return verify_wl<1, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 2: return verify_wl<2, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 3: return verify_wl<3, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 4: return verify_wl<4, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 5: return verify_wl<5, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 6: return verify_wl<6, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 7: return verify_wl<7, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 8: return verify_wl<8, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 9: return verify_wl<9, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 10: return verify_wl<10, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 11: return verify_wl<11, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 12: return verify_wl<12, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 13: return verify_wl<13, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 14: return verify_wl<14, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 15: return verify_wl<15, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 16: return verify_wl<16, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -524,13 +565,14 @@ hipError_t verify_l(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, 
 }  // namespace
 
 hipError_t launch_verify(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
-                         uint32_t *list, uint32_t *groups, uint32_t *count, uint32_t words,
-                         uint32_t layout, int cus, hipStream_t s)
+                         uint32_t *list, uint32_t *groups, uint32_t *deferred, uint32_t *count,
+                         uint32_t words, uint32_t layout, int cus, hipStream_t s)
 {
     return layout == GK_READS_INTERLEAVED
-               ? verify_l<GK_READS_INTERLEAVED>(a, accept, dist, list, groups, count, words, cus,
-                                                s)
-               : verify_l<GK_READS_SPLIT>(a, accept, dist, list, groups, count, words, cus, s);
+               ? verify_l<GK_READS_INTERLEAVED>(a, accept, dist, list, groups, deferred, count,
+                                                words, cus, s)
+               : verify_l<GK_READS_SPLIT>(a, accept, dist, list, groups, deferred, count, words,
+                                          cus, s);
 }
 
 }  // namespace gkd

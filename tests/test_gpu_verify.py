@@ -123,6 +123,53 @@ def test_verify_uniform_waves(gkctx, m, e):
     assert np.any(want <= e) and np.any(want == e + 1)
 
 
+@pytest.mark.parametrize("m,e", [(64, 0), (128, 3), (200, 7), (256, 5)])
+def test_verify_paired_mixed_waves(gkctx, m, e):
+    """A batch-wide e <= 7 on reads of up to 256 bases: waves whose pairs all
+    share one length run two pairs per band word; waves with another length
+    among them, and waves of random lengths, are handed to the one-pair
+    kernel; pairs that fail the gate (unknown base, empty read, window past the
+    end, read index out of range) give GK_EST_NONE on either path.  The kinds
+    cycle every 64 pairs, so each launch holds all of them."""
+    rng = np.random.default_rng(5000 + m + e)
+    ref = gen.c0_reference()
+    gk.gk_load_reference(gkctx, ref)
+    n = 6000
+    reads, off, pr, pos, _ = edited_pairs(rng, ref, n, max_len=m, min_len=m)
+    seqs = [reads[off[i]:off[i + 1]].tobytes() for i in range(n)]
+    kind = (np.arange(n) // 64) % 4
+    status = np.zeros(n, bool)
+    for i in range(n):
+        if kind[i] == 1 and i % 64 == 17:                  # one odd length in the wave
+            seqs[i] = seqs[i][:m - 1 - int(rng.integers(0, min(m - 1, 9)))]
+        elif kind[i] == 2 and i % 5 == 0:                  # gate failures among equals
+            c = (i // 5) % 4
+            status[i] = True
+            if c == 0:
+                s_ = bytearray(seqs[i])
+                s_[int(rng.integers(0, m))] = ord("N")
+                seqs[i] = bytes(s_)
+            elif c == 1:
+                seqs[i] = b""
+            elif c == 2:
+                pos[i] = len(ref) - m // 2
+            else:
+                pr[i] = n + 7
+        elif kind[i] == 3:                                 # random lengths
+            seqs[i] = seqs[i][:int(rng.integers(1, m + 1))]
+    reads, off = concat_reads(seqs)
+    ev = np.full(n, e, np.uint8)
+    ok = ~status
+    want = np.full(n, gk.GK_EST_NONE, np.uint16)
+    want[ok] = oracle_dist(ref, reads, off, pr[ok], pos[ok], ev[ok])
+    say(f"case: verify paired mixed waves m={m} e={e}")
+    d = verify(gkctx, reads, off, pr, pos, None, m, e_uniform=e)
+    bad = np.nonzero(d != want)[0]
+    assert len(bad) == 0, (f"{len(bad)} differ; first {bad[0]} (kind {kind[bad[0]]}): gpu "
+                           f"{d[bad[0]]} want {want[bad[0]]}")
+    assert np.any(want[ok] <= e) and np.any(want == e + 1)
+
+
 def test_verify_after_filter_and_status(gkctx):
     """Only GK_ACCEPT pairs are verified; rejected, undefined (unknown base,
     window past the end) and invalid pairs give GK_EST_NONE."""
