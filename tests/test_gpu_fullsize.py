@@ -6,6 +6,7 @@ import pytest
 import torch
 
 import gen
+import oracle
 from gpu_cases import assert_same, run_oracle, say
 from paper_2103_14978_amd import device, gk
 
@@ -28,6 +29,29 @@ def sample_check(ref, ps, a, s, e, k, seed, label):
     assert_same(a[idx], s[idx], ra, rs, label)
 
 
+def verify_check(ctx, ref, ps, b, dp, a, e, k, seed, label):
+    """gk_verify after the filter, as the benchmark calls it: GK_EST_NONE on
+    every pair the filter did not accept, at most e + 1 on every accepted
+    one, and the oracle's capped edit distance on a sample of the accepted."""
+    dist = torch.empty(ps.n_pairs, dtype=torch.int16, device="cuda")
+    gk.gk_verify(ctx, b, dp.accept, dist, None)
+    torch.cuda.synchronize()
+    d = dist.cpu().numpy().view(np.uint16)
+    acc = a == gk.GK_ACCEPT
+    assert np.all(d[~acc] == gk.GK_EST_NONE), label
+    assert np.all(d[acc] <= e + 1), label
+    rng = np.random.default_rng(seed)
+    idx = np.nonzero(acc)[0]
+    idx = np.sort(rng.choice(idx, size=min(len(idx), k), replace=False))
+    want = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[idx],
+                                    ps.cand_pos[idx], e, n_threads=gen.default_threads())
+    bad = np.nonzero(d[idx] != want)[0]
+    assert len(bad) == 0, (f"{label}: {len(bad)} of {len(idx)} differ; first pair "
+                           f"{idx[bad[0]]}: gpu {d[idx[bad[0]]]} oracle {want[bad[0]]}")
+    assert np.any(want <= e), label
+    return want
+
+
 @pytest.fixture(scope="module")
 def ref100m():
     return gen.c1_reference()
@@ -43,12 +67,16 @@ def test_config1_full(gkctx, ref100m):
     say("case: config1 full 2^24 e=5")
     dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=100)
     dp = device.upload_pairs(None, ps.cand_pos)
-    gk.gk_filter(gkctx, device.batch_for(dr, dp, e_uniform=5, max_read_len=100), None)
+    b = device.batch_for(dr, dp, e_uniform=5, max_read_len=100)
+    gk.gk_filter(gkctx, b, None)
     torch.cuda.synchronize()
     a, s = device.results(dp)
     check_properties(a, s, 5, 100, "config1")
     ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, 5)
     assert_same(a, s, ra, rs, "config1 every pair")
+    say("case: config1 full verify of the accepted pairs")
+    want = verify_check(gkctx, ref, ps, b, dp, a, 5, 1 << 15, 11, "config1 verify")
+    assert np.any(want == 6)          # false accepts reach the cap
 
 
 @pytest.mark.parametrize("m,es", [(150, (3, 7, 15)), (250, (5, 12, 25))])
@@ -61,12 +89,15 @@ def test_config2_full(gkctx, ref100m, m, es):
         say(f"case: config2 full m={m} e={e} pairs={ps.n_pairs}")
         dr = device.encode_reads(gkctx, ps.reads, ps.read_off, max_len=m)
         dp = device.upload_pairs(ps.pair_read, ps.cand_pos)
-        gk.gk_filter(gkctx, device.batch_for(dr, dp, e_uniform=e, max_read_len=m), None)
+        b = device.batch_for(dr, dp, e_uniform=e, max_read_len=m)
+        gk.gk_filter(gkctx, b, None)
         torch.cuda.synchronize()
         a, s = device.results(dp)
         check_properties(a, s, e, m, f"config2 m={m} e={e}")
         sample_check(ref, ps, a, s, e, 1 << 13, e, f"config2 m={m} e={e}")
-        del dr, dp
+        say(f"case: config2 full verify m={m} e={e}")
+        verify_check(gkctx, ref, ps, b, dp, a, e, 1 << 13, 100 + e, f"config2 verify m={m} e={e}")
+        del dr, dp, b
 
 
 def test_config3_full(gkctx, ref100m):
