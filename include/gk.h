@@ -422,7 +422,11 @@ int gk_server_submit(gk_server *srv, const gk_request *req, uint64_t *ticket);
 
 /* Wait for a ticket (timeout_us < 0: no limit).  GK_ETIMEOUT leaves the
    request queued (wait again); any other return releases the ticket.
-   Returns the request's status; stats may be NULL.  Thread-safe. */
+   Returns the request's status; stats may be NULL.  Thread-safe.
+   After a HIP error inside the server, every queued or in-flight request
+   ends: GK_OK if its results were already copied out, else GK_EDEVICE.  No
+   copy touches its host buffers once its wait has returned.  Later submits
+   return GK_EDEVICE, and so does gk_server_stop. */
 int gk_server_wait(gk_server *srv, uint64_t ticket, int64_t timeout_us,
                    gk_request_stats *stats);
 

@@ -148,6 +148,11 @@ struct gk_server {
     gkd::MixedArgs margs{};
     uint64_t ticks = 0, tick_req_max = 0, pairs_done = 0;
     int tick_buf = 0;
+    bool completing = false;               // the completer holds inflight.front()
+    // Failure injection for tests of the error paths, with no GPU fault: the
+    // loader's k-th load, or the completer's k-th tick, reports an error as a
+    // failed HIP call would (0 = never).
+    uint64_t fail_load_at = 0, fail_tick_at = 0, loads = 0, ticks_taken = 0;
 };
 
 namespace {
@@ -275,18 +280,26 @@ void finish(gk_server *s, Req *q, int status)
 
 void fail_all(gk_server *s, const std::string &msg)
 {
-    // caller holds s->mu: a device error ends the server's work
+    // Caller holds s->mu: a device error ends the server's work.  Requests
+    // are finished (so their waits return GK_EDEVICE) only once no copy can
+    // still touch their host buffers: the copy streams are drained first,
+    // and the tick the completer is copying out stays with the completer.
+    // The loader and the scheduler finish the requests they hold themselves.
     s->err = msg;
+    (void)hipStreamSynchronize(s->s_copy);
+    if (s->s_copy2)
+        (void)hipStreamSynchronize(s->s_copy2);
     for (auto *q : s->pending)
         finish(s, q, GK_EDEVICE);
     for (auto *q : s->ready)
         finish(s, q, GK_EDEVICE);
-    for (auto &t : s->inflight)
-        for (auto *q : t.reqs)
+    const size_t keep = s->completing && !s->inflight.empty() ? 1 : 0;
+    for (size_t i = keep; i < s->inflight.size(); ++i)
+        for (auto *q : s->inflight[i].reqs)
             finish(s, q, GK_EDEVICE);
     s->pending.clear();
     s->ready.clear();
-    s->inflight.clear();
+    s->inflight.erase(s->inflight.begin() + keep, s->inflight.end());
     s->stopping = true;
     s->cv.notify_all();
 }
@@ -324,6 +337,7 @@ void loader_main(gk_server *s)
         q->arena_off = off;
         q->t_admit = now_us();
         place(s, q);
+        const bool inject = s->fail_load_at != 0 && ++s->loads == s->fail_load_at;
         lk.unlock();
 
         // Batched mode alternates two copy streams, so one request's
@@ -332,6 +346,8 @@ void loader_main(gk_server *s)
         if (s->mode == GK_SERVER_BATCHED && (s->admitted++ & 1u))
             st = s->s_copy2;
         hipError_t e = load_request(s, q, st);
+        if (e == hipSuccess && inject)
+            e = hipErrorInvalidValue;
         if (s->mode == GK_SERVER_SEQUENTIAL) {
             // One request at a time on one stream: copy in, encode, filter, copy out.
             if (e == hipSuccess) {
@@ -340,8 +356,9 @@ void loader_main(gk_server *s)
             }
             if (e == hipSuccess)
                 e = copy_out(q, s->s_copy);
+            const hipError_t es = hipStreamSynchronize(s->s_copy);   // always drained
             if (e == hipSuccess)
-                e = hipStreamSynchronize(s->s_copy);
+                e = es;
             lk.lock();
             if (e != hipSuccess) {
                 finish(s, q, GK_EDEVICE);
@@ -355,9 +372,17 @@ void loader_main(gk_server *s)
         if (e == hipSuccess)
             e = hipEventRecord(q->ready, st);
         lk.lock();
-        if (e != hipSuccess) {
+        if (e != hipSuccess || s->stopping) {
+            // A failure here, or in another thread while this request was
+            // loading: its copies are drained before its wait can return.
+            lk.unlock();
+            (void)hipStreamSynchronize(st);
+            lk.lock();
             finish(s, q, GK_EDEVICE);
-            fail_all(s, std::string("server load: ") + hipGetErrorName(e));
+            if (e != hipSuccess)
+                fail_all(s, std::string("server load: ") + hipGetErrorName(e));
+            else
+                s->cv.notify_all();
             break;
         }
         s->ready.push_back(q);
@@ -410,9 +435,20 @@ void scheduler_main(gk_server *s)
         if (e == hipSuccess)
             e = hipEventRecord(s->tick_done[t.buf], s->s_compute);
         lk.lock();
-        if (e != hipSuccess) {
-            s->inflight.push_back(std::move(t));
-            fail_all(s, std::string("server tick: ") + hipGetErrorName(e));
+        if (e != hipSuccess || s->stopping) {
+            // A failure here, or in another thread meanwhile (the completer
+            // may have gone): this tick's requests end here, after what was
+            // launched for them.
+            lk.unlock();
+            (void)hipStreamSynchronize(s->s_compute);
+            lk.lock();
+            for (auto *q : t.reqs)
+                finish(s, q, GK_EDEVICE);
+            s->buf_busy[t.buf] = false;
+            if (e != hipSuccess)
+                fail_all(s, std::string("server tick: ") + hipGetErrorName(e));
+            else
+                s->cv.notify_all();
             break;
         }
         s->ticks++;
@@ -432,6 +468,8 @@ void completer_main(gk_server *s)
         if (s->inflight.empty() && s->stopping)
             break;
         Tick t = s->inflight.front();
+        s->completing = true;
+        const bool inject = s->fail_tick_at != 0 && ++s->ticks_taken == s->fail_tick_at;
         lk.unlock();
         hipError_t e = hipEventSynchronize(s->tick_done[t.buf]);
         const bool released = e == hipSuccess;
@@ -447,12 +485,14 @@ void completer_main(gk_server *s)
         for (auto *q : t.reqs)
             if (e == hipSuccess)
                 e = copy_out(q, s->s_d2h);
+        const hipError_t es = hipStreamSynchronize(s->s_d2h);     // always drained
         if (e == hipSuccess)
-            e = hipStreamSynchronize(s->s_d2h);
+            e = es;
+        if (e == hipSuccess && inject)
+            e = hipErrorInvalidValue;
         lk.lock();
-        if (s->inflight.empty())     // failed and cleared by another thread
-            continue;
-        s->inflight.pop_front();
+        s->completing = false;
+        s->inflight.pop_front();     // fail_all leaves the tick being completed
         for (auto *q : t.reqs)
             finish(s, q, e == hipSuccess ? GK_OK : GK_EDEVICE);
         if (!released)
@@ -468,6 +508,11 @@ void completer_main(gk_server *s)
 void destroy_server(gk_server *s)
 {
     DeviceScope dev(s->ctx->device);
+    // After a failure, ticks launched before it may still run: nothing the
+    // server's streams use is freed before they are drained.
+    for (hipStream_t st : {s->s_copy, s->s_copy2, s->s_compute, s->s_d2h})
+        if (st)
+            (void)hipStreamSynchronize(st);
     for (int k = 0; k < 2; ++k) {
         if (s->graph[k])
             (void)hipGraphExecDestroy(s->graph[k]);
@@ -723,5 +768,19 @@ int gk_server_stop(gk_server *s)
 }
 
 int64_t gk_clock_us(void) { return now_us(); }
+
+// For tests of the error paths (no GPU fault): the server's load number
+// `load_at` (counted from 1 in admission order), or its completed tick number
+// `tick_at`, fails as a failed HIP call would; 0 leaves that point alone.
+// Call before submitting requests.
+int gk_detail_server_inject_failure(gk_server *s, uint64_t load_at, uint64_t tick_at)
+{
+    if (!s)
+        return GK_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->fail_load_at = load_at;
+    s->fail_tick_at = tick_at;
+    return GK_OK;
+}
 
 }  // extern "C"

@@ -2,6 +2,8 @@
 single byte.  Each request's results alone equal its results in the mix
 (tolerance: bit-identical) and the oracle's; the sequential per-request mode
 gives the same bytes; admission limits queue requests instead of failing."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -166,3 +168,54 @@ def test_stop_cancels_unadmitted(gkctx, served):
     t = time.time()
     gk.gk_server_stop(srv)
     assert time.time() - t < 30
+
+
+@pytest.mark.parametrize("mode,load_at,tick_at", [(gk.GK_SERVER_BATCHED, 12, 0),
+                                                  (gk.GK_SERVER_BATCHED, 0, 2),
+                                                  (gk.GK_SERVER_SEQUENTIAL, 5, 0)])
+def test_injected_failure_ends_every_wait(gkctx, served, mode, load_at, tick_at):
+    """A HIP call inside the server that reports an error (injected on the
+    host: every kernel runs normally) ends the server's work without leaving
+    a wait behind: every wait returns, GK_OK with the oracle's results for
+    requests done before the failure and GK_EDEVICE for the rest; later
+    submissions are refused and stop reports GK_EDEVICE."""
+    ref, reqs, want = served
+    gk.gk_load_reference(gkctx, ref)
+    say(f"case: server injected failure mode={mode} load_at={load_at} tick_at={tick_at}")
+    srv = gk.gk_server_start(gkctx, 1 << 30, 64, 256, mode)
+    inject = gk.lib().gk_detail_server_inject_failure
+    inject.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64]
+    inject.restype = ctypes.c_int
+    stopped = False
+    try:
+        assert inject(srv, load_at, tick_at) == gk.GK_OK
+        objs = [gk.Request(ps.reads, ps.read_off, ps.cand_pos, e, pair_read=ps.pair_read)
+                for ps, e in reqs]
+        tickets = []
+        for o in objs:
+            try:
+                tickets.append(gk.gk_server_submit(srv, o))
+            except gk.GkError as err:            # the failure came first
+                assert err.status == gk.GK_EDEVICE
+                break
+        statuses = []
+        for k, t in enumerate(tickets):
+            st, _ = gk.gk_server_wait(srv, t, 60_000_000)
+            assert st in (gk.GK_OK, gk.GK_EDEVICE), st
+            statuses.append(st)
+            if st == gk.GK_OK:
+                assert_same(objs[k].accept, objs[k].est, *want[k], f"request {k}")
+        assert gk.GK_EDEVICE in statuses
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_server_submit(srv, objs[0])
+        assert ei.value.status == gk.GK_EDEVICE
+        stopped = True
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_server_stop(srv)
+        assert ei.value.status == gk.GK_EDEVICE
+    finally:
+        if not stopped:
+            try:
+                gk.gk_server_stop(srv)
+            except gk.GkError:
+                pass
