@@ -542,7 +542,7 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
         return st;
     a.stream_reads = 0;     // the mixed kernel reads each pair entry twice
     const uint32_t wmax = (b->max_read_len + 31) / 32;
-    gkd::MixedArgs x;
+    gkd::MixedArgs x{};   // zeroed: its bytes are part of the graph key
     if ((st = mixed_args(ctx, ctx->mixed, wmax, b->read_layout, x)) != GK_OK)
         return st;
     hipError_t e;
@@ -750,7 +750,7 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_
             for (uint32_t sort_e : {0u, 1u})
                 for (uint32_t bpc : {0u, (uint32_t)std::max(1, full_bpc / 2)}) {
                     MixedConfig c{tile, ppl, sort_e, bpc};
-                    gkd::MixedArgs x;
+                    gkd::MixedArgs x{};
                     if ((st = mixed_args(ctx, c, wmax, b->read_layout, x)) != GK_OK) {
                         (void)hipEventDestroy(e0);
                         (void)hipEventDestroy(e1);
