@@ -170,6 +170,33 @@ def test_verify_paired_mixed_waves(gkctx, m, e):
     assert np.any(want[ok] <= e) and np.any(want == e + 1)
 
 
+def test_verify_paired_deferral_at_scale(gkctx):
+    """2^21 pairs of four read lengths (64-128 bp) with a batch-wide e = 4,
+    every pair verified: the paired kernel's persistent loop runs several
+    steps per lane, nearly every wave defers its pairs to the one-pair
+    kernel, and the deferred list fills from many waves at once.  Every
+    distance is at most e + 1; a sample equals the oracle's."""
+    ref = gen.c1_reference(20_000_000)
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.pairs(ref, seed=4242, n_reads=320_000, lengths=[64, 80, 100, 128],
+                   cand_kind=gen.CAND_GEOM, cand_param=1 / 8, cand_cap=64, true_frac=0.5,
+                   edit_kind=gen.EDIT_RATE, edit_param=1.2, e_value=4,
+                   band_cands=True).take_pairs(1 << 21)
+    n = ps.n_pairs
+    assert n == 1 << 21
+    say(f"case: verify paired deferral at scale, {n} pairs, e=4")
+    d = verify(gkctx, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, None, 128, e_uniform=4)
+    assert np.all(d <= 5)
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(n, size=1 << 14, replace=False))
+    want = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[idx],
+                                    ps.cand_pos[idx], 4, n_threads=gen.default_threads())
+    bad = np.nonzero(d[idx] != want)[0]
+    assert len(bad) == 0, (f"{len(bad)} differ; first pair {idx[bad[0]]}: gpu "
+                           f"{d[idx[bad[0]]]} oracle {want[bad[0]]}")
+    assert np.any(want <= 4) and np.any(want == 5)
+
+
 def test_verify_after_filter_and_status(gkctx):
     """Only GK_ACCEPT pairs are verified; rejected, undefined (unknown base,
     window past the end) and invalid pairs give GK_EST_NONE."""
