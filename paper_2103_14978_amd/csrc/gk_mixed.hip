@@ -352,6 +352,8 @@ hipError_t launch_mixed_wl(const FilterArgs &a, const MixedArgs &x0, hipStream_t
         const uint64_t n = a.n_pairs - first < CHUNK ? a.n_pairs - first : CHUNK;
         c.n_pairs = n;
         c.pair_read = a.pair_read ? a.pair_read + first : nullptr;
+        if (!a.pair_read && first > 0)
+            c.n_reads = 0;   // pair i uses read i < n_reads < 2^30: none here
         c.cand_pos = a.cand_pos + first;
         c.e_pair = a.e_pair ? a.e_pair + first : nullptr;
         c.accept = a.accept + first;

@@ -259,3 +259,52 @@ def test_beyond_2e30_pairs(gkctx):
     assert np.array_equal(d[acc], want)
     del dist, dp, dr, b, pr, pos, a, s
     torch.cuda.empty_cache()
+
+
+def test_beyond_2e30_identity(gkctx):
+    """2^30 + 4133 pairs with no pair-to-read map (pair i uses read i) over
+    4096 reads: the first 4096 pairs are compared, every other pair is
+    GK_INVALID, also past the 2^30 split where each launch numbers its pairs
+    from 0 again.  Plain and mixed launches and gk_verify (every pair)."""
+    import oracle
+    n = (1 << 30) + 4133
+    m, e, n_reads = 100, 5, 4096
+    rng = np.random.default_rng(2031)
+    ref = gen.c1_reference(20_000_000)
+    gk.gk_load_reference(gkctx, ref)
+    origins = rng.integers(8, len(ref) - m - 8, n_reads)
+    from gpu_cases import concat_reads
+    reads, off = concat_reads([ref[o:o + m].tobytes() for o in origins])
+    pos = rng.integers(0, len(ref) - m, n, dtype=np.uint32)
+    pos[:n_reads:2] = origins[::2].astype(np.uint32)      # half of them at their origin
+    say(f"case: beyond 2^30 identity, n_pairs={n}")
+    dr = device.encode_reads(gkctx, reads, off, max_len=m)
+    dp = device.upload_pairs(None, pos)
+    b = device.batch_for(dr, dp, e_uniform=e, max_read_len=m)
+    gk.gk_filter(gkctx, b, None)
+    torch.cuda.synchronize()
+    a, s = device.results(dp)
+    pr = np.arange(n_reads, dtype=np.uint32)
+    ra, rs = run_oracle(ref, reads, off, pr, pos[:n_reads], e)
+    assert_same(a[:n_reads], s[:n_reads], ra, rs, "identity, pairs with a read")
+    assert np.all(a[n_reads:] == gk.GK_INVALID), "pairs without a read"
+    assert np.all(s[n_reads:] == gk.GK_EST_NONE)
+    for opt, val in ((gk.GK_OPT_MIXED_TILE, 4096), (gk.GK_OPT_MIXED_PAIRS_PER_LANE, 1),
+                     (gk.GK_OPT_MIXED_SORT_E, 1), (gk.GK_OPT_MIXED_BLOCKS_PER_CU, 0)):
+        gk.gk_set_option(gkctx, opt, val)
+    dp.accept.fill_(0xEE)
+    gk.gk_filter_mixed(gkctx, b, None)
+    torch.cuda.synchronize()
+    a2, s2 = device.results(dp)
+    assert np.array_equal(a2, a) and np.array_equal(s2, s), "mixed differs from plain"
+    del a2, s2
+    dist = torch.empty(n, dtype=torch.int16, device="cuda")
+    gk.gk_verify(gkctx, b, None, dist, None)
+    torch.cuda.synchronize()
+    d = dist.cpu().numpy().view(np.uint16)
+    want = oracle.levenshtein_batch(reads, off, ref, pr, pos[:n_reads], e,
+                                    n_threads=gen.default_threads())
+    assert np.array_equal(d[:n_reads], want)
+    assert np.all(d[n_reads:] == gk.GK_EST_NONE)
+    del dist, d, dp, dr, b, pos, a, s
+    torch.cuda.empty_cache()
