@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void k_verify(FilterArgs a, const uint32_t *li
     }
 }
 
-// Persistent over the list, two entries per lane per step (t and t + stride),
+// Persistent over the list, two entries per lane per step (t and t + 64),
 // for batches with one e <= 7 and reads of up to 8 words.  When every pair of
 // the wave that passes the gate has the length and e of the wave's first such
 // pair, each lane's two pairs share a 32-bit band word (band_distance2); pairs
@@ -268,12 +268,16 @@ __global__ __launch_bounds__(256) void k_verify_paired(FilterArgs a, const uint3
                                                        uint32_t *deferred_count)
 {
     const uint32_t n = *count;
-    const uint32_t stride = gridDim.x * 256u;
     const uint32_t lane = threadIdx.x & 63u;
-    for (uint32_t t = blockIdx.x * 256u + threadIdx.x; t < n; t += 2u * stride) {
-        const bool has1 = t + stride < n;
+    // A wave takes blocks of 128 consecutive list entries, a lane entries
+    // lane and lane + 64 of the block: the list orders each listing group by
+    // read length, so the two halves of a block mostly share one.
+    const uint32_t first = (blockIdx.x * 4u + (threadIdx.x >> 6)) * 128u + lane;
+    const uint32_t step = gridDim.x * 4u * 128u;
+    for (uint32_t t = first; t < n; t += step) {
+        const bool has1 = t + 64u < n;
         const uint32_t i0 = list[t];
-        const uint32_t i1 = has1 ? list[t + stride] : i0;
+        const uint32_t i1 = has1 ? list[t + 64u] : i0;
         const PairIdx p0 = load_idx(a, i0);
         const PairIdx p1 = load_idx(a, i1);
         PairData<W> d0, d1;
@@ -323,12 +327,14 @@ __global__ __launch_bounds__(256) void k_verify_paired(FilterArgs a, const uint3
 }
 
 // Listing the pairs to verify (accept[i] == GK_ACCEPT, or every pair when
-// accept is NULL) in pair order, without a contended counter: a workgroup
-// covers 4096 consecutive pairs, 16 per lane (one 16-byte load of accept when
-// VEC); k_select_count stores each workgroup's count, k_select_scan turns the
+// accept is NULL) without a contended counter: a workgroup covers 4096
+// consecutive pairs, 16 per lane (one 16-byte load of accept when VEC);
+// k_select_count stores each workgroup's count, k_select_scan turns the
 // counts into offsets (and the total into *count), k_select_write puts each
-// workgroup's pairs at its offset through LDS.  VEC needs accept and dist
-// aligned to 16 bytes; the host checks.
+// workgroup's pairs at its offset through LDS: in pair order when they all
+// have one read length, else ordered by read length, so that the waves of the
+// verify kernels see one length (their fast paths need it).  VEC needs accept
+// and dist aligned to 16 bytes; the host checks.
 constexpr uint32_t SEL_PER_LANE = 16u, SEL_PER_GROUP = 256u * SEL_PER_LANE;
 
 // Bit j of the result: pair i0 + j is listed.  With fill, the 16 dist entries
@@ -420,26 +426,76 @@ __global__ __launch_bounds__(1024) void k_select_scan(uint32_t *group_count, uin
     }
 }
 
+// Sort keys of the 16 pairs i0 .. i0 + 15 a lane lists (bit j of sel): the
+// read length when a pair can be compared at it (1..max_read_len), else 0 (it
+// fails the gate).  With no pair-to-read map the 16 lengths are consecutive
+// and come in two 16-byte loads when aligned.
+__device__ __forceinline__ void length_keys(const FilterArgs &a, uint32_t i0, uint32_t sel,
+                                            uint32_t (&key)[SEL_PER_LANE])
+{
+    if (a.pair_read == nullptr && i0 + SEL_PER_LANE <= a.n_reads &&
+        ((uintptr_t)(a.read_len + i0) & 15u) == 0u) {
+        const uint4 v0 = *reinterpret_cast<const uint4 *>(a.read_len + i0);
+        const uint4 v1 = *reinterpret_cast<const uint4 *>(a.read_len + i0 + 8);
+        const uint32_t w[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+#pragma unroll
+        for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+            key[j] = (w[j >> 1] >> (16u * (j & 1u))) & 0xFFFFu;
+    } else {
+#pragma unroll
+        for (uint32_t j = 0; j < SEL_PER_LANE; ++j) {
+            key[j] = 0u;
+            if (sel & (1u << j)) {
+                const uint32_t r = a.pair_read ? a.pair_read[i0 + j] : i0 + j;
+                key[j] = r < a.n_reads ? (uint32_t)a.read_len[r] : 0u;
+            }
+        }
+    }
+#pragma unroll
+    for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+        key[j] = key[j] <= a.max_read_len ? key[j] : 0u;
+}
+
 template <bool VEC>
-__global__ __launch_bounds__(256) void k_select_write(const uint8_t *accept, uint32_t n,
-                                                      const uint32_t *group_offset,
+__global__ __launch_bounds__(256) void k_select_write(FilterArgs a, const uint8_t *accept,
+                                                      uint32_t n, const uint32_t *group_offset,
                                                       uint32_t *list)
 {
     __shared__ uint32_t stage[SEL_PER_GROUP];
-    __shared__ uint32_t wave_sum[4];
+    __shared__ uint16_t key[SEL_PER_GROUP];
+    __shared__ uint32_t hist[GK_MAX_READ_LEN + 1];
+    __shared__ uint32_t wave_sum[4], wave_min[4], wave_max[4];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t i0 = blockIdx.x * SEL_PER_GROUP + threadIdx.x * SEL_PER_LANE;
     const uint32_t sel = select_bits<VEC>(accept, n, i0, nullptr, false);
+    uint32_t k16[SEL_PER_LANE];
+    length_keys(a, i0, sel, k16);
     const uint32_t c = (uint32_t)__popc(sel);
-    uint32_t incl = c;
+    uint32_t incl = c, lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+    for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+        if (sel & (1u << j)) {
+            lo = k16[j] < lo ? k16[j] : lo;
+            hi = k16[j] > hi ? k16[j] : hi;
+        }
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
         const uint32_t t = __shfl_up(incl, o, 64);
         if (lane >= (uint32_t)o)
             incl += t;
     }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t ol = __shfl_xor(lo, o, 64), oh = __shfl_xor(hi, o, 64);
+        lo = ol < lo ? ol : lo;
+        hi = oh > hi ? oh : hi;
+    }
     if (lane == 63u)
         wave_sum[wave] = incl;
+    if (lane == 0u) {
+        wave_min[wave] = lo;
+        wave_max[wave] = hi;
+    }
     __syncthreads();
     const uint32_t total = wave_sum[0] + wave_sum[1] + wave_sum[2] + wave_sum[3];
     uint32_t at = incl - c;
@@ -447,12 +503,55 @@ __global__ __launch_bounds__(256) void k_select_write(const uint8_t *accept, uin
         at += wave_sum[w];
 #pragma unroll
     for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
-        if (sel & (1u << j))
-            stage[at++] = i0 + j;
+        if (sel & (1u << j)) {
+            stage[at] = i0 + j;
+            key[at] = (uint16_t)k16[j];
+            ++at;
+        }
+    uint32_t kmin = wave_min[0], kmax = wave_max[0];
+    for (uint32_t w = 1; w < 4u; ++w) {
+        kmin = wave_min[w] < kmin ? wave_min[w] : kmin;
+        kmax = wave_max[w] > kmax ? wave_max[w] : kmax;
+    }
+    const uint32_t nb = kmin < kmax ? kmax - kmin + 1u : 0u;
+    for (uint32_t b = threadIdx.x; b < nb; b += 256u)
+        hist[b] = 0u;
     __syncthreads();
     const uint32_t base = group_offset[blockIdx.x];
+    if (nb == 0u) {                      // one length (or nothing listed): pair order
+        for (uint32_t t = threadIdx.x; t < total; t += 256u)
+            list[base + t] = stage[t];
+        return;
+    }
+    // Counting sort by key over [kmin, kmax] (the order within a key does not
+    // matter: every result is written at its own pair index).
     for (uint32_t t = threadIdx.x; t < total; t += 256u)
-        list[base + t] = stage[t];
+        atomicAdd(&hist[key[t] - kmin], 1u);
+    __syncthreads();
+    if (wave == 0u) {                    // exclusive prefix sums of the buckets
+        const uint32_t per = (nb + 63u) / 64u;
+        const uint32_t b0 = lane * per < nb ? lane * per : nb;
+        const uint32_t b1 = b0 + per < nb ? b0 + per : nb;
+        uint32_t sum = 0;
+        for (uint32_t b = b0; b < b1; ++b)
+            sum += hist[b];
+        uint32_t run = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(run, o, 64);
+            if (lane >= (uint32_t)o)
+                run += t;
+        }
+        run -= sum;
+        for (uint32_t b = b0; b < b1; ++b) {
+            const uint32_t v = hist[b];
+            hist[b] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < total; t += 256u)
+        list[base + atomicAdd(&hist[key[t] - kmin], 1u)] = stage[t];
 }
 
 // Resident 256-lane workgroups per CU of k_verify (PAIRED false) or
@@ -493,6 +592,8 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
         const uint64_t n = a.n_pairs - first < CHUNK ? a.n_pairs - first : CHUNK;
         c.n_pairs = n;
         c.pair_read = a.pair_read ? a.pair_read + first : nullptr;
+        if (!a.pair_read && first > 0)
+            c.n_reads = 0;   // pair i uses read i < n_reads < 2^30: none here
         c.cand_pos = a.cand_pos + first;
         c.e_pair = a.e_pair ? a.e_pair + first : nullptr;
         c.accept = nullptr;
@@ -511,10 +612,10 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
                                (uint32_t)n, groups_buf, out);
         hipLaunchKernelGGL(k_select_scan, dim3(1), dim3(1024), 0, s, groups_buf, groups, count);
         if (vec)
-            hipLaunchKernelGGL(k_select_write<true>, dim3(groups), dim3(256), 0, s, acc,
+            hipLaunchKernelGGL(k_select_write<true>, dim3(groups), dim3(256), 0, s, c, acc,
                                (uint32_t)n, groups_buf, list);
         else
-            hipLaunchKernelGGL(k_select_write<false>, dim3(groups), dim3(256), 0, s, acc,
+            hipLaunchKernelGGL(k_select_write<false>, dim3(groups), dim3(256), 0, s, c, acc,
                                (uint32_t)n, groups_buf, list);
         const uint64_t vb1 = want < (uint64_t)cus * per_cu1 ? want : (uint64_t)cus * per_cu1;
         if (paired) {

@@ -125,12 +125,13 @@ def test_verify_uniform_waves(gkctx, m, e):
 
 @pytest.mark.parametrize("m,e", [(64, 0), (128, 3), (200, 7), (256, 5)])
 def test_verify_paired_mixed_waves(gkctx, m, e):
-    """A batch-wide e <= 7 on reads of up to 256 bases: waves whose pairs all
-    share one length run two pairs per band word; waves with another length
-    among them, and waves of random lengths, are handed to the one-pair
-    kernel; pairs that fail the gate (unknown base, empty read, window past the
-    end, read index out of range) give GK_EST_NONE on either path.  The kinds
-    cycle every 64 pairs, so each launch holds all of them."""
+    """A batch-wide e <= 7 on reads of up to 256 bases, with runs of one
+    length, single odd lengths, gate failures (unknown base, empty read,
+    window past the end, read index out of range) and random lengths cycling
+    every 64 pairs.  The listing orders each group by length, so blocks of
+    one length run two pairs per band word, and blocks that straddle two of
+    the many short length runs are handed to the one-pair kernel; gate
+    failures give GK_EST_NONE on either path."""
     rng = np.random.default_rng(5000 + m + e)
     ref = gen.c0_reference()
     gk.gk_load_reference(gkctx, ref)
@@ -172,10 +173,11 @@ def test_verify_paired_mixed_waves(gkctx, m, e):
 
 def test_verify_paired_deferral_at_scale(gkctx):
     """2^21 pairs of four read lengths (64-128 bp) with a batch-wide e = 4,
-    every pair verified: the paired kernel's persistent loop runs several
-    steps per lane, nearly every wave defers its pairs to the one-pair
-    kernel, and the deferred list fills from many waves at once.  Every
-    distance is at most e + 1; a sample equals the oracle's."""
+    every pair verified: each listing group is ordered by length, the paired
+    kernel's persistent loop runs several steps per lane, and the blocks that
+    straddle two lengths (in every group) go to the one-pair kernel through
+    the deferred list.  Every distance is at most e + 1; a sample equals the
+    oracle's."""
     ref = gen.c1_reference(20_000_000)
     gk.gk_load_reference(gkctx, ref)
     ps = gen.pairs(ref, seed=4242, n_reads=320_000, lengths=[64, 80, 100, 128],
