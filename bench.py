@@ -317,6 +317,38 @@ def main() -> int:
         log(f"verify {ms_after:.3f} ms for {accepted} accepted pairs; filter+verify "
             f"{ms_fv:.3f} ms vs verify-all {ms_all:.3f} ms")
         del dist
+        # Reads of several lengths under one e (trimmed reads, say): 2^21
+        # pairs of 64/80/100/128 bp, every pair verified, beside 2^21 pairs of
+        # 100 bp from the same generator.
+        ml = {}
+        for label, lengths in (("four_lengths", [64, 80, 100, 128]), ("one_length", [100])):
+            mps = gen.pairs(ref, seed=4242, n_reads=320_000, lengths=lengths,
+                            cand_kind=gen.CAND_GEOM, cand_param=1 / 8, cand_cap=64,
+                            true_frac=0.5, edit_kind=gen.EDIT_RATE, edit_param=1.2, e_value=4,
+                            band_cands=True).take_pairs(1 << 21)
+            mdr = device.encode_reads(ctx, mps.reads, mps.read_off, max_len=128)
+            mdp = device.upload_pairs(mps.pair_read, mps.cand_pos)
+            mb = device.batch_for(mdr, mdp, e_uniform=4, max_read_len=128)
+            mdist = torch.empty(mps.n_pairs, dtype=torch.int16, device=dev)
+            torch.cuda.synchronize()
+            ms_m = timed_ms(lambda: gk.gk_verify(ctx, mb, None, mdist, stream), vk)
+            entry = {"pairs": int(mps.n_pairs), "verify_all_ms": round(ms_m, 4)}
+            if not args.no_parity:
+                import oracle
+                gk.gk_verify(ctx, mb, None, mdist, stream)
+                torch.cuda.synchronize()
+                md = mdist.cpu().numpy().view(np.uint16)
+                rng = np.random.default_rng(4243)
+                idx = np.sort(rng.choice(mps.n_pairs, size=1 << 12, replace=False))
+                want = oracle.levenshtein_batch(mps.reads, mps.read_off, ref,
+                                                mps.pair_read[idx], mps.cand_pos[idx], 4,
+                                                n_threads=gen.default_threads())
+                entry["sampled_mismatches"] = int(np.sum(md[idx] != want))
+            ml[label] = entry
+            del mdist, mb, mdp, mdr
+        verify["mixed_lengths"] = dict(ml, e=4, what="gk_verify of every pair")
+        log(f"verify-all, four lengths {ml['four_lengths']['verify_all_ms']:.3f} ms, "
+            f"one length {ml['one_length']['verify_all_ms']:.3f} ms (2^21 pairs)")
 
     # Filter time (Sec. 4.3): host ASCII reads and candidates in pinned host
     # memory -> gk_filter_host (chunked copies in, device encoding, filter,
