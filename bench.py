@@ -756,6 +756,30 @@ def bench_mixed(args, log) -> int:
                                      ps.cand_pos[idx], ps.e[idx], n_threads=gen.default_threads())
         parity.update(sampled_pairs=int(len(idx)),
                       mismatches=int(np.sum((a_m[idx] != ra) | (s_m[idx] != rs))))
+    # Verification of this batch's accepted pairs (mixed lengths, per-pair e),
+    # with sampled parity against the oracle's capped edit distance.
+    vmix = None
+    if not args.no_verify:
+        vdist = torch.empty(n_pairs, dtype=torch.int16, device="cuda")
+        _, k_v = timed(lambda: gk.gk_verify(ctx, batch, dp.accept, vdist, stream), steps, 1)
+        acc_idx = np.nonzero(a_m == gk.GK_ACCEPT)[0]
+        vmix = {"accepted_pairs": int(len(acc_idx)), "verify_ms": round(k_v * 1e3, 4),
+                "accepted_pairs_per_s": round(len(acc_idx) / k_v, 1)}
+        if not args.no_parity:
+            import oracle
+            vd = vdist.cpu().numpy().view(np.uint16)
+            rng = np.random.default_rng(8)
+            idx = np.sort(rng.choice(acc_idx, size=min(len(acc_idx), 1 << 14), replace=False))
+            vm = 0
+            for ev in np.unique(ps.e[idx]):
+                sub = idx[ps.e[idx] == ev]
+                want = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[sub],
+                                                ps.cand_pos[sub], int(ev),
+                                                n_threads=gen.default_threads())
+                vm += int(np.sum(vd[sub] != want))
+            vmix.update(sampled_pairs=int(len(idx)), sampled_mismatches=vm)
+        log(f"verify of {len(acc_idx)} accepted pairs: {k_v * 1e3:.3f} ms")
+        del vdist
     w = (m_pair + 31) // 32
     ops = int(np.sum(14 * (2 * np.minimum(e_pair, m_pair - 1) + 1) * w + 6 * w + 16))
     achieved = ops / k_m / 1e12
@@ -788,6 +812,7 @@ def bench_mixed(args, log) -> int:
                      "ops_per_pair_mean": round(ops / n_pairs, 1),
                      "kernel_ms": round(k_m * 1e3, 4), "kernel_source_hash": mhash},
         "parity": parity,
+        "verification": vmix,
     }
     print(json.dumps(out), flush=True)
     gk.gk_destroy(ctx)

@@ -428,7 +428,7 @@ __global__ __launch_bounds__(1024) void k_select_scan(uint32_t *group_count, uin
 
 // Sort keys of the 16 pairs i0 .. i0 + 15 a lane lists (bit j of sel): the
 // read length when a pair can be compared at it (1..max_read_len), else 0 (it
-// fails the gate).  With no pair-to-read map the 16 lengths are consecutive
+// fails the gate); with a per-pair e, twice that plus whether e > 15.  With no pair-to-read map the 16 lengths are consecutive
 // and come in two 16-byte loads when aligned.
 __device__ __forceinline__ void length_keys(const FilterArgs &a, uint32_t i0, uint32_t sel,
                                             uint32_t (&key)[SEL_PER_LANE])
@@ -454,6 +454,13 @@ __device__ __forceinline__ void length_keys(const FilterArgs &a, uint32_t i0, ui
 #pragma unroll
     for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
         key[j] = key[j] <= a.max_read_len ? key[j] : 0u;
+    // With a per-pair e, pairs on the 32-bit band (e <= 15) and on the 64-bit
+    // one are kept apart too, so that a wave runs one band width.
+    if (a.e_pair) {
+#pragma unroll
+        for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+            key[j] = 2u * key[j] + ((sel & (1u << j)) && a.e_pair[i0 + j] > 15u ? 1u : 0u);
+    }
 }
 
 template <bool VEC>
@@ -463,7 +470,7 @@ __global__ __launch_bounds__(256) void k_select_write(FilterArgs a, const uint8_
 {
     __shared__ uint32_t stage[SEL_PER_GROUP];
     __shared__ uint16_t key[SEL_PER_GROUP];
-    __shared__ uint32_t hist[GK_MAX_READ_LEN + 1];
+    __shared__ uint32_t hist[2u * GK_MAX_READ_LEN + 2u];
     __shared__ uint32_t wave_sum[4], wave_min[4], wave_max[4];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     const uint32_t i0 = blockIdx.x * SEL_PER_GROUP + threadIdx.x * SEL_PER_LANE;
