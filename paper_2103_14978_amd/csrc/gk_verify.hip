@@ -441,6 +441,22 @@ __device__ __forceinline__ void length_keys(const FilterArgs &a, uint32_t i0, ui
 #pragma unroll
         for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
             key[j] = (w[j >> 1] >> (16u * (j & 1u))) & 0xFFFFu;
+    } else if (a.pair_read != nullptr && sel != 0u && i0 + SEL_PER_LANE <= a.n_pairs &&
+               ((uintptr_t)(a.pair_read + i0) & 15u) == 0u) {
+        // the 16 read indices in four 16-byte loads (one 64-byte span), the
+        // lengths of the listed pairs only
+        uint32_t r[SEL_PER_LANE];
+#pragma unroll
+        for (uint32_t q = 0; q < 4u; ++q) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(a.pair_read + i0 + 4u * q);
+            r[4u * q] = v.x;
+            r[4u * q + 1u] = v.y;
+            r[4u * q + 2u] = v.z;
+            r[4u * q + 3u] = v.w;
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+            key[j] = (sel & (1u << j)) && r[j] < a.n_reads ? (uint32_t)a.read_len[r[j]] : 0u;
     } else {
 #pragma unroll
         for (uint32_t j = 0; j < SEL_PER_LANE; ++j) {
