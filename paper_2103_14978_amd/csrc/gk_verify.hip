@@ -332,8 +332,9 @@ __global__ __launch_bounds__(256) void k_verify_paired(FilterArgs a, const uint3
 // k_select_count stores each workgroup's count, k_select_scan turns the
 // counts into offsets (and the total into *count), k_select_write puts each
 // workgroup's pairs at its offset through LDS: in pair order when they all
-// have one read length, else ordered by read length, so that the waves of the
-// verify kernels see one length (their fast paths need it).  VEC needs accept
+// have one sort key, else ordered by key (read length; with a per-pair e,
+// also whether e > 15), so that the waves of the verify kernels see one
+// length and one band width (their fast paths need it).  VEC needs accept
 // and dist aligned to 16 bytes; the host checks.
 constexpr uint32_t SEL_PER_LANE = 16u, SEL_PER_GROUP = 256u * SEL_PER_LANE;
 
