@@ -485,8 +485,8 @@ __global__ __launch_bounds__(256) void k_select_write(FilterArgs a, const uint8_
                                                       uint32_t n, const uint32_t *group_offset,
                                                       uint32_t *list)
 {
+    // stage[t]: sort key << 12 | the pair's offset in the group (< 4096)
     __shared__ uint32_t stage[SEL_PER_GROUP];
-    __shared__ uint16_t key[SEL_PER_GROUP];
     __shared__ uint32_t hist[2u * GK_MAX_READ_LEN + 2u];
     __shared__ uint32_t wave_sum[4], wave_min[4], wave_max[4];
     const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
@@ -525,13 +525,11 @@ __global__ __launch_bounds__(256) void k_select_write(FilterArgs a, const uint8_
     uint32_t at = incl - c;
     for (uint32_t w = 0; w < wave; ++w)
         at += wave_sum[w];
+    const uint32_t g0 = blockIdx.x * SEL_PER_GROUP;
 #pragma unroll
     for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
-        if (sel & (1u << j)) {
-            stage[at] = i0 + j;
-            key[at] = (uint16_t)k16[j];
-            ++at;
-        }
+        if (sel & (1u << j))
+            stage[at++] = (k16[j] << 12) | (i0 + j - g0);
     uint32_t kmin = wave_min[0], kmax = wave_max[0];
     for (uint32_t w = 1; w < 4u; ++w) {
         kmin = wave_min[w] < kmin ? wave_min[w] : kmin;
@@ -542,15 +540,15 @@ __global__ __launch_bounds__(256) void k_select_write(FilterArgs a, const uint8_
         hist[b] = 0u;
     __syncthreads();
     const uint32_t base = group_offset[blockIdx.x];
-    if (nb == 0u) {                      // one length (or nothing listed): pair order
+    if (nb == 0u) {                      // one key (or nothing listed): pair order
         for (uint32_t t = threadIdx.x; t < total; t += 256u)
-            list[base + t] = stage[t];
+            list[base + t] = g0 + (stage[t] & 4095u);
         return;
     }
     // Counting sort by key over [kmin, kmax] (the order within a key does not
     // matter: every result is written at its own pair index).
     for (uint32_t t = threadIdx.x; t < total; t += 256u)
-        atomicAdd(&hist[key[t] - kmin], 1u);
+        atomicAdd(&hist[(stage[t] >> 12) - kmin], 1u);
     __syncthreads();
     if (wave == 0u) {                    // exclusive prefix sums of the buckets
         const uint32_t per = (nb + 63u) / 64u;
@@ -574,8 +572,10 @@ __global__ __launch_bounds__(256) void k_select_write(FilterArgs a, const uint8_
         }
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < total; t += 256u)
-        list[base + atomicAdd(&hist[key[t] - kmin], 1u)] = stage[t];
+    for (uint32_t t = threadIdx.x; t < total; t += 256u) {
+        const uint32_t v = stage[t];
+        list[base + atomicAdd(&hist[(v >> 12) - kmin], 1u)] = g0 + (v & 4095u);
+    }
 }
 
 // Resident 256-lane workgroups per CU of k_verify (PAIRED false) or
