@@ -641,14 +641,20 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
         else
             hipLaunchKernelGGL(k_select_write<false>, dim3(groups), dim3(256), 0, s, c, acc,
                                (uint32_t)n, groups_buf, list);
-        const uint64_t vb1 = want < (uint64_t)cus * per_cu1 ? want : (uint64_t)cus * per_cu1;
+        // Grids of up to 8 times the resident workgroups: later workgroups
+        // start as earlier ones finish, so the waves' gathers do not all come
+        // at once (measured faster than one resident round at every sweep
+        // point; the list length is only known on the device).
+        const uint64_t vb1 = want < 8ull * cus * per_cu1 ? want : 8ull * cus * per_cu1;
         if (paired) {
             const uint64_t want2 = (n + 511) / 512;        // two pairs per lane
-            const uint64_t vb = want2 < (uint64_t)cus * per_cu ? want2 : (uint64_t)cus * per_cu;
+            const uint64_t vb = want2 < 8ull * cus * per_cu ? want2 : 8ull * cus * per_cu;
             hipLaunchKernelGGL((k_verify_paired<W, L>), dim3((uint32_t)vb), dim3(256), 0, s, c,
                                list, count, out, deferred, count + 1);
-            // the waves it could not pair (count[1] entries, usually none)
-            hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vb1), dim3(256), 0, s, c,
+            // the waves it could not pair (count[1] entries, usually none:
+            // one resident round)
+            const uint64_t vbd = want < (uint64_t)cus * per_cu1 ? want : (uint64_t)cus * per_cu1;
+            hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vbd), dim3(256), 0, s, c,
                                (const uint32_t *)deferred, (const uint32_t *)(count + 1), out);
         } else {
             hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vb1), dim3(256), 0, s, c, list,
