@@ -123,6 +123,70 @@ def plain_kernel_name(words: int, e: int, pairs_per_lane: int) -> str:
     return f"k_filter_single<{words}" if pairs_per_lane == 1 else f"k_filter<{words}"
 
 
+def measure_peaks(log):
+    """The device's measured VALU issue rate for the instruction kinds the
+    filter is made of (3-input bit select, funnel shift, 2-input XOR, and-or,
+    or3), in lane-ops/s, and its device copy rate, from the calibration
+    kernels of libgk_calib.so.  The roofline takes max(spec, measured)."""
+    import ctypes
+    from paper_2103_14978_amd import build as hipbuild
+    if not os.path.exists(hipbuild.CALIB_LIB):
+        raise ImportError(f"{hipbuild.CALIB_LIB} is missing: build the package first")
+    L = ctypes.CDLL(hipbuild.CALIB_LIB)
+    d = ctypes.c_double
+    L.gkc_valu_rate.argtypes = [ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                ctypes.POINTER(d), ctypes.POINTER(d)]
+    L.gkc_copy_rate.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(d),
+                                ctypes.POINTER(d)]
+    kinds = {0: "v_bfi_b32", 1: "v_alignbit_b32", 2: "v_xor_b32", 3: "v_and_or_b32",
+             4: "v_or3_b32"}
+    valu = {}
+    for k, name in kinds.items():
+        rate, ms = d(), d()
+        st = L.gkc_valu_rate(k, 8, 4096, 3, ctypes.byref(rate), ctypes.byref(ms))
+        if st != 0:
+            raise RuntimeError(f"gkc_valu_rate({name}) failed: {st}")
+        valu[name] = round(rate.value / 1e12, 3)
+    rate, ms = d(), d()
+    st = L.gkc_copy_rate(2 << 30, 5, ctypes.byref(rate), ctypes.byref(ms))
+    if st != 0:
+        raise RuntimeError(f"gkc_copy_rate failed: {st}")
+    out = {"valu_Tops": valu, "valu_measured_Tops": max(valu.values()),
+           "copy_GBs": round(rate.value / 1e9, 1),
+           "what": "8 independent chains per lane of one instruction kind, 8 workgroups of "
+                   "256 lanes per CU, best of 3; copy: 2 GiB read + 2 GiB written, best of 5"}
+    log(f"calibration: VALU {valu} T lane-ops/s; copy {out['copy_GBs']} GB/s")
+    return out
+
+
+def events_ms(fn, k: int, stream, warm: int = 2, stats: bool = False):
+    """Mean milliseconds of fn() over k runs, each bracketed by HIP events on
+    `stream` (the stream fn launches on), after `warm` untimed runs.  With
+    stats: (mean, min, median)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(k)]
+    for a0, a1 in ev:
+        a0.record(stream)
+        fn()
+        a1.record(stream)
+    torch.cuda.synchronize()
+    t = [a0.elapsed_time(a1) for a0, a1 in ev]
+    if stats:
+        return float(np.mean(t)), float(np.min(t)), float(np.median(t))
+    return float(np.mean(t))
+
+
+def encode_bytes_per_read(m: int, rows: int) -> int:
+    """Algorithmic HBM bytes per read of gk_encode_reads: the ASCII text (m B)
+    and its offset (8 B) in; rows packed words (4 B each), the length (2 B)
+    and the unknown-base flag (1 B) out."""
+    return m + 8 + 4 * rows + 2 + 1
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +203,11 @@ def main() -> int:
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-verify", action="store_true",
                     help="skip the verification (edit distance) measurement")
+    ap.add_argument("--no-calibrate", action="store_true",
+                    help="skip the VALU / copy calibration kernels (the roofline then takes "
+                         "the spec peak)")
+    ap.add_argument("--no-device-encoded", action="store_true",
+                    help="skip the device-encoded (encode + filter) measurement")
     ap.add_argument("--no-ft", action="store_true",
                     help="skip the host-to-host filter-time measurement")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -192,6 +261,8 @@ def main() -> int:
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    calib = None if args.no_calibrate else measure_peaks(log)
 
     if args.workload == "mixed":
         return bench_mixed(args, log)
@@ -252,6 +323,61 @@ def main() -> int:
     log(f"{args.steps} steps in {wall:.4f}s; kernel avg {k_avg_s * 1e3:.4f} ms "
         f"(min {min(kernel_ms):.4f}, max {max(kernel_ms):.4f})")
 
+    # Device-encoded kernel time (the paper's device-encoded rows of Table 2):
+    # ASCII reads and their offsets resident in HBM, each run encodes them
+    # (gk_encode_reads) and filters (gk_filter); mean of 10 runs.  The encode
+    # kernel is also timed alone for its HBM roofline.
+    dev_enc = None
+    if not args.no_device_encoded:
+        d_ascii = torch.from_numpy(np.ascontiguousarray(ps.reads)).to(dev)
+        d_off = torch.from_numpy(ps.read_off.view(np.int64)).to(dev)
+        rows = (m + 15) // 16
+        packed2 = torch.full_like(dr.packed, -1)
+        len2 = torch.full_like(dr.read_len, -1)
+        hn2 = torch.full_like(dr.has_n, 0xFF)
+        batch2 = gk.make_batch(n_reads=dr.n_reads, pitch=dr.pitch, max_read_len=m,
+                               reads=packed2, read_len=len2, read_has_n=hn2,
+                               n_pairs=n_pairs, pair_read=dp.pair_read, cand_pos=dp.cand_pos,
+                               accept=dp.accept, est=dp.est, e_uniform=e, read_layout=layout)
+
+        def enc():
+            gk.gk_encode_reads(ctx, d_ascii, d_off, ps.n_reads, dr.pitch, rows, layout,
+                               packed2, len2, hn2, stream)
+
+        def enc_filter():
+            enc()
+            gk.gk_filter(ctx, batch2, stream)
+        a_ref, s_ref = device.results(dp)
+        enc_ms, enc_min, enc_med = events_ms(enc, 10, stream, warm=3, stats=True)
+        ef_ms, ef_min, ef_med = events_ms(enc_filter, 10, stream, warm=3, stats=True)
+        a2, s2 = device.results(dp)
+        nr = ps.n_reads
+        same_words = bool(torch.equal(packed2.view(rows, -1)[:, :nr],
+                                      dr.packed.view(rows, -1)[:, :nr])
+                          and torch.equal(len2[:nr], dr.read_len[:nr])
+                          and torch.equal(hn2[:nr], dr.has_n[:nr]))
+        res_mism = int(np.sum((a2 != a_ref) | (s2 != s_ref)))
+        eb = encode_bytes_per_read(m, rows) * ps.n_reads
+        enc_gbs = eb / (enc_ms / 1e3) / 1e9
+        dev_enc = {"pairs_per_s": round(n_pairs / (ef_ms / 1e3), 1),
+                   "ms_per_step": round(ef_ms, 4), "ms_min": round(ef_min, 4),
+                   "ms_median": round(ef_med, 4), "runs": 10,
+                   "encode_ms": round(enc_ms, 4), "encode_ms_min": round(enc_min, 4),
+                   "encode_ms_median": round(enc_med, 4),
+                   "encode_roofline": {"bound": "hbm", "kernel": "k_encode_reads_staged",
+                                       "achieved": round(enc_gbs, 1), "peak": HBM_PEAK_GBS,
+                                       "unit": "GB/s", "frac": round(enc_gbs / HBM_PEAK_GBS, 4),
+                                       "bytes_per_read": encode_bytes_per_read(m, rows)},
+                   "words_identical_to_resident": same_words,
+                   "mismatches_vs_kernel_path": res_mism,
+                   "what": "ASCII reads + offsets resident in HBM: gk_encode_reads then "
+                           "gk_filter per run, HIP events on the launch stream"}
+        log(f"device-encoded: encode {enc_ms:.4f} ms ({enc_gbs:.0f} GB/s), encode+filter "
+            f"{ef_ms:.4f} ms ({n_pairs / (ef_ms / 1e3) / 1e9:.2f} G pairs/s), words identical "
+            f"{same_words}, "
+            f"{res_mism} result mismatches")
+        del d_ascii, d_off, packed2, len2, hn2, batch2
+
     # Parity on a random sample of this run's outputs (bit-exact); the CPU
     # baseline below widens it to every pair the oracle is timed on.
     parity = None
@@ -275,17 +401,7 @@ def main() -> int:
         dist = torch.empty(n_pairs, dtype=torch.int16, device=dev)
 
         def timed_ms(fn, k):
-            for _ in range(2):
-                fn()
-            torch.cuda.synchronize()
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(k)]
-            for a0, a1 in ev:
-                a0.record(stream)
-                fn()
-                a1.record(stream)
-            torch.cuda.synchronize()
-            return float(np.mean([a0.elapsed_time(a1) for a0, a1 in ev]))
+            return events_ms(fn, k, stream)
         vk = max(3, args.steps // 10)
         ms_after = timed_ms(lambda: gk.gk_verify(ctx, batch, dp.accept, dist, stream), vk)
         ms_fv = timed_ms(lambda: (gk.gk_filter(ctx, batch, stream),
@@ -446,9 +562,13 @@ def main() -> int:
     khash = kernel_source_hash()
     kname = plain_kernel_name((m + 31) // 32, e, args.pairs_per_lane)
     traffic = traffic_from_profile(khash, n_pairs, kernel=kname)
+    peak = max(VALU_PEAK_TOPS, calib["valu_measured_Tops"]) if calib else VALU_PEAK_TOPS
     roofline = {"bound": "alu", "kernel": kname + ">", "achieved": round(achieved_tops, 3),
-                "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
-                "frac": round(achieved_tops / VALU_PEAK_TOPS, 4), "traffic": traffic,
+                "peak": round(peak, 3), "unit": "Tops/s",
+                "frac": round(achieved_tops / peak, 4), "traffic": traffic,
+                "peak_spec": round(VALU_PEAK_TOPS, 3),
+                "peak_measured": calib["valu_measured_Tops"] if calib else None,
+                "calibration": calib,
                 "traffic_GBs": (round(traffic / k_avg_s / 1e9, 1) if traffic else None),
                 "ops_per_pair": ops_per_pair(m, e), "kernel_ms": round(k_avg_s * 1e3, 4),
                 "kernel_ms_min": round(float(np.min(kernel_ms)), 4),
@@ -514,6 +634,7 @@ def main() -> int:
         "kernel_pairs_per_s": round(n_pairs / k_avg_s, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "device_encoded": dev_enc,
         "filter_time": ft,
         "verification": verify,
         "parity": parity,

@@ -11,6 +11,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgk.so")
+CALIB_LIB = os.path.join(HERE, "libgk_calib.so")   # roofline calibration kernels
+CALIB_SOURCES = ["gk_calib.hip"]
+LOADGEN_LIB = os.path.join(HERE, "libgk_loadgen.so")  # served-bench load generator
+LOADGEN_SOURCES = ["gk_loadgen.cpp"]                   # host-only, links libgk.so
 SOURCES = ["gk_api.hip", "gk_encode.hip", "gk_filter.hip", "gk_host.hip", "gk_mixed.hip",
            "gk_reference.hip", "gk_server.hip", "gk_verify.hip"]
 HOST_SOURCES = ["gk_host_encode.cpp"]     # host-only C++ (no device code)
@@ -43,17 +47,30 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES) + len(HOST_SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES + HOST_SOURCES))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
+    srcs = SOURCES + HOST_SOURCES + CALIB_SOURCES + LOADGEN_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=len(srcs)) as ex:
+        objs = dict(zip(srcs, ex.map(_compile, srcs)))
+    for lib, parts in ((LIB, SOURCES + HOST_SOURCES), (CALIB_LIB, CALIB_SOURCES)):
+        tmp = lib + ".tmp"
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread",
+               *[objs[p] for p in parts], "-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError(f"hipcc link failed for {os.path.basename(lib)}")
+        os.replace(tmp, lib)
+        if verbose:
+            print(f"built {lib}")
+    tmp = LOADGEN_LIB + ".tmp"
+    cmd = [CXX, "-shared", "-fPIC", "-pthread", objs[LOADGEN_SOURCES[0]], "-L", HERE, "-lgk",
+           "-Wl,-rpath,$ORIGIN", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc link failed")
-    os.replace(tmp, LIB)
+        raise RuntimeError("link failed for libgk_loadgen.so")
+    os.replace(tmp, LOADGEN_LIB)
     if verbose:
-        print(f"built {LIB}")
+        print(f"built {LOADGEN_LIB}")
     return LIB
 
 

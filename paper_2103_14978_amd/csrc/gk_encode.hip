@@ -44,18 +44,14 @@ __device__ __forceinline__ void load16(const uint8_t *p, uint32_t n, uint32_t (&
     }
 }
 
+// One read's rows packed words straight from global memory (any alignment,
+// any offsets).  Returns 1 if a byte other than A/C/G/T is among the read's
+// first 16 * rows bytes.
 template <uint32_t LAYOUT>
-__global__ __launch_bounds__(256) void k_encode_reads(const uint8_t *ascii,
-                                                      const uint64_t *read_off, uint32_t n_reads,
-                                                      uint32_t pitch, uint32_t rows,
-                                                      uint32_t *packed, uint16_t *len_out,
-                                                      uint8_t *has_n_out)
+__device__ __forceinline__ uint32_t encode_direct(const uint8_t *ascii, uint64_t off, uint64_t len,
+                                                  uint32_t r, uint32_t pitch, uint32_t rows,
+                                                  uint32_t *packed)
 {
-    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
-    if (r >= n_reads)
-        return;
-    const uint64_t off = read_off[r];
-    const uint64_t len = read_off[r + 1] - off;
     uint32_t unknown = 0;
     for (uint32_t w = 0; w < rows; ++w) {
         uint32_t word = 0;
@@ -78,6 +74,232 @@ __global__ __launch_bounds__(256) void k_encode_reads(const uint8_t *ascii,
             }
         }
         packed[(size_t)w * pitch + r] = word;
+    }
+    return unknown;
+}
+
+// Fallback encoder: one lane per read, straight from global memory.  Used
+// when the ASCII buffer is not 16-byte aligned.
+template <uint32_t LAYOUT>
+__global__ __launch_bounds__(256) void k_encode_reads(const uint8_t *ascii,
+                                                      const uint64_t *read_off, uint32_t n_reads,
+                                                      uint32_t pitch, uint32_t rows,
+                                                      uint32_t *packed, uint16_t *len_out,
+                                                      uint8_t *has_n_out)
+{
+    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+    if (r >= n_reads)
+        return;
+    const uint64_t off = read_off[r];
+    const uint64_t len = read_off[r + 1] - off;
+    const uint32_t unknown = encode_direct<LAYOUT>(ascii, off, len, r, pitch, rows, packed);
+    len_out[r] = (uint16_t)(len < 0xFFFFu ? len : 0xFFFFu);
+    if (has_n_out)
+        has_n_out[r] = (uint8_t)unknown;
+}
+
+// ---- staged encoder -------------------------------------------------------
+//
+// A workgroup takes ENC_G consecutive reads.  Their text is one contiguous
+// span of the ASCII buffer; the workgroup reads it with aligned 16-byte loads
+// (consecutive lanes, consecutive bytes), turns every 32 bytes into three
+// 32-bit planes in LDS (low code bits, high code bits, unknown bases; base b
+// of the group at bit b), and then each lane cuts its own read's words out of
+// the planes with funnel shifts and writes them to the transposed rows, where
+// the lanes' stores are consecutive.  The planes take a quarter of the text's
+// bytes, so every read length up to 512 fits.
+
+constexpr uint32_t ENC_G = 256;
+
+__host__ __device__ inline uint32_t enc_cap_words(uint32_t rows)
+{
+    // 32-base words of the longest span staged: ENC_G reads of 16 * rows
+    // bases, plus one word for the span's start alignment.
+    return ENC_G * 16u * rows / 32u + 1u;
+}
+
+// Bytes of dynamic LDS: three planes of cap + 1 words (the extra word is a
+// zero sentinel after the span).
+__host__ inline size_t enc_lds_bytes(uint32_t rows) { return 3u * (enc_cap_words(rows) + 1u) * 4u; }
+
+// The 32 bytes of a staging chunk at p (16-byte aligned).  Bytes at or beyond
+// `n` are not needed; dwords holding none of the first n bytes are not read.
+__device__ __forceinline__ void load_chunk(const uint8_t *p, uint32_t n, uint32_t (&d)[8])
+{
+    if (n >= 32u) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 a = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        const u32x4 b = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p) + 1);
+        d[0] = a.x, d[1] = a.y, d[2] = a.z, d[3] = a.w;
+        d[4] = b.x, d[5] = b.y, d[6] = b.z, d[7] = b.w;
+    } else {
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
+#pragma unroll
+        for (uint32_t j = 0; j < 8; ++j)
+            d[j] = 4u * j < n ? q[j] : 0u;
+    }
+}
+
+// Planes of 32 ASCII bytes (d[i] holds bytes 4i .. 4i+3, byte 4i+k at bits
+// 8k).  A base's code is bits 1-2 of (c ^ (c >> 1)) for the letters
+// A C G T a c g t; a byte is a base iff it equals, up to case, the letter its
+// code names.  Bits of the four bytes of a dword are gathered with a byte dot
+// product against powers of two.
+__device__ __forceinline__ void chunk_planes(const uint32_t (&d)[8], uint32_t n, uint32_t &lo,
+                                             uint32_t &hi, uint32_t &un)
+{
+    uint32_t x[8], bad_any = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        x[i] = d[i] ^ (d[i] >> 1);
+        // the letter (lower case) each byte's code names: codes 0..3 select
+        // bytes 0 and 2 of the second operand, 0 and 2 of the first
+        const uint32_t letter = __builtin_amdgcn_perm(0x00740067u, 0x00630061u, x[i] & 0x06060606u);
+        bad_any |= (d[i] ^ letter) & 0xDFDFDFDFu;
+    }
+    // byte j of the result: the pair of dwords 2j, 2j+1 (bits of value 2 or 4)
+    uint32_t bl[4], bh[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        bl[j] = __builtin_amdgcn_udot4(x[2 * j] & 0x02020202u, 0x08040201u,
+                                       __builtin_amdgcn_udot4(x[2 * j + 1] & 0x02020202u,
+                                                              0x80402010u, 0u, false),
+                                       false);
+        bh[j] = __builtin_amdgcn_udot4(x[2 * j] & 0x04040404u, 0x08040201u,
+                                       __builtin_amdgcn_udot4(x[2 * j + 1] & 0x04040404u,
+                                                              0x80402010u, 0u, false),
+                                       false);
+    }
+    // bl[j] = 2 * byte, bh[j] = 4 * byte
+    lo = (bl[0] >> 1) | (bl[1] << 7) | (bl[2] << 15) | (bl[3] << 23);
+    hi = (bh[0] >> 2) | (bh[1] << 6) | (bh[2] << 14) | (bh[3] << 22);
+    un = 0;
+    if (bad_any) {
+        // per byte: 1 if it differs from its letter in any bit but the case bit
+        uint32_t bu[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint32_t f[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = 2 * j + h;
+                const uint32_t letter =
+                    __builtin_amdgcn_perm(0x00740067u, 0x00630061u, x[i] & 0x06060606u);
+                const uint32_t mm = (d[i] ^ letter) & 0xDFDFDFDFu;
+                f[h] = ((((mm & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | mm) >> 7) & 0x01010101u;
+            }
+            bu[j] = __builtin_amdgcn_udot4(f[0], 0x08040201u,
+                                           __builtin_amdgcn_udot4(f[1], 0x80402010u, 0u, false),
+                                           false);
+        }
+        un = bu[0] | (bu[1] << 8) | (bu[2] << 16) | (bu[3] << 24);
+    }
+    if (n < 32u) {
+        const uint32_t keep = (1u << n) - 1u;
+        lo &= keep;
+        hi &= keep;
+        un &= keep;
+    }
+}
+
+template <uint32_t LAYOUT>
+__device__ __forceinline__ uint32_t pack_half(uint32_t lo16, uint32_t hi16)
+{
+    if (LAYOUT == GK_READS_SPLIT)
+        return lo16 | (hi16 << 16);
+    // interleaved: code bits of base j at 2j (low) and 2j+1 (high)
+    uint32_t a = lo16, b = hi16;
+    a = (a | (a << 8)) & 0x00FF00FFu;
+    a = (a | (a << 4)) & 0x0F0F0F0Fu;
+    a = (a | (a << 2)) & 0x33333333u;
+    a = (a | (a << 1)) & 0x55555555u;
+    b = (b | (b << 8)) & 0x00FF00FFu;
+    b = (b | (b << 4)) & 0x0F0F0F0Fu;
+    b = (b | (b << 2)) & 0x33333333u;
+    b = (b | (b << 1)) & 0x55555555u;
+    return a | (b << 1);
+}
+
+template <uint32_t LAYOUT>
+__global__ __launch_bounds__(256) void k_encode_reads_staged(const uint8_t *ascii,
+                                                             const uint64_t *read_off,
+                                                             uint32_t n_reads, uint32_t pitch,
+                                                             uint32_t rows, uint32_t *packed,
+                                                             uint16_t *len_out,
+                                                             uint8_t *has_n_out)
+{
+    extern __shared__ uint32_t enc_lds[];
+    const uint32_t cap = enc_cap_words(rows);
+    uint32_t *p_lo = enc_lds;
+    uint32_t *p_hi = enc_lds + (cap + 1u);
+    uint32_t *p_un = enc_lds + 2u * (cap + 1u);
+
+    const uint32_t r0 = blockIdx.x * ENC_G;
+    const uint32_t r1 = n_reads - r0 < ENC_G ? n_reads : r0 + ENC_G;
+    const uint64_t base = read_off[r0];
+    const uint64_t end = read_off[r1];
+    const uint64_t a0 = base & ~31ull;                  // span start, 32-byte aligned
+    // Staged when the span is in order and fits (reads longer than 16 * rows
+    // bases, or offsets out of order, take the direct path).
+    const bool staged = end >= base && end - a0 <= 32ull * cap;
+    uint32_t nw = 0;
+    if (staged) {
+        nw = (uint32_t)((end - a0 + 31u) / 32u);
+        for (uint32_t j = threadIdx.x; j < nw; j += 256u) {
+            const uint64_t at = a0 + 32ull * j;
+            const uint32_t n = end - at < 32u ? (uint32_t)(end - at) : 32u;
+            uint32_t d[8];
+            load_chunk(ascii + at, n, d);
+            uint32_t lo, hi, un;
+            chunk_planes(d, n, lo, hi, un);
+            p_lo[j] = lo;
+            p_hi[j] = hi;
+            p_un[j] = un;
+        }
+        if (threadIdx.x == 0) {
+            p_lo[nw] = 0u;
+            p_hi[nw] = 0u;
+            p_un[nw] = 0u;
+        }
+    }
+    __syncthreads();
+
+    const uint32_t r = r0 + threadIdx.x;
+    if (r >= r1)
+        return;
+    const uint64_t off = read_off[r];
+    const uint64_t len = read_off[r + 1] - off;
+    const uint64_t use = len < 16ull * rows ? len : 16ull * rows;     // bases encoded
+    uint32_t unknown;
+    if (staged && off >= base && off + use <= end && use <= len) {
+        const uint32_t p0 = (uint32_t)(off - a0);
+        const uint32_t q = p0 >> 5, sh = p0 & 31u;
+        const uint32_t u = (uint32_t)use;
+        uint32_t un_any = 0;
+        uint32_t l_prev = p_lo[q], h_prev = p_hi[q], n_prev = p_un[q];
+        for (uint32_t w2 = 0; 2u * w2 < rows; ++w2) {
+            // 32 bases from p0 + 32 w2: words q + w2 and q + w2 + 1 (the
+            // sentinel or later text past the span: masked below)
+            const uint32_t qn = q + w2 + 1u <= nw ? q + w2 + 1u : nw;
+            const uint32_t l_next = p_lo[qn], h_next = p_hi[qn], n_next = p_un[qn];
+            uint32_t lo = __builtin_amdgcn_alignbit(l_next, l_prev, sh);
+            uint32_t hi = __builtin_amdgcn_alignbit(h_next, h_prev, sh);
+            uint32_t un = __builtin_amdgcn_alignbit(n_next, n_prev, sh);
+            const uint32_t have = u > 32u * w2 ? u - 32u * w2 : 0u;
+            const uint32_t keep = have >= 32u ? 0xFFFFFFFFu : (1u << have) - 1u;
+            lo &= keep;
+            hi &= keep;
+            un_any |= un & keep;
+            packed[(size_t)(2u * w2) * pitch + r] = pack_half<LAYOUT>(lo & 0xFFFFu, hi & 0xFFFFu);
+            if (2u * w2 + 1u < rows)
+                packed[(size_t)(2u * w2 + 1u) * pitch + r] = pack_half<LAYOUT>(lo >> 16, hi >> 16);
+            l_prev = l_next;
+            h_prev = h_next;
+            n_prev = n_next;
+        }
+        unknown = un_any ? 1u : 0u;
+    } else {
+        unknown = encode_direct<LAYOUT>(ascii, off, len, r, pitch, rows, packed);
     }
     len_out[r] = (uint16_t)(len < 0xFFFFu ? len : 0xFFFFu);
     if (has_n_out)
@@ -126,18 +348,31 @@ __global__ __launch_bounds__(256) void k_pack_reference(const uint8_t *ascii, ui
         atomicAdd(counter, (unsigned long long)c);
 }
 
-// One lane per read: its rows consecutive words in, one word per transposed
-// row out (the writes of a wave to one row are consecutive).
+// Host-encoded rows to the transposed layout.  A workgroup takes ENC_G
+// reads, reads their rows * ENC_G words as one contiguous run (consecutive
+// lanes, consecutive words) into LDS, and then writes each row with
+// consecutive lanes.  inv_rows = ceil(2^32 / rows), so that g / rows =
+// (g * inv_rows) >> 32 for every word index g of a workgroup (g < 2^13).
 __global__ __launch_bounds__(256) void k_transpose_reads(const uint32_t *rowmajor,
                                                          uint32_t n_reads, uint32_t rows,
-                                                         uint32_t pitch, uint32_t *out)
+                                                         uint32_t pitch, uint64_t inv_rows,
+                                                         uint32_t *out)
 {
-    const uint32_t r = blockIdx.x * 256u + threadIdx.x;
-    if (r >= n_reads)
-        return;
-    const uint32_t *src = rowmajor + (size_t)r * rows;
-    for (uint32_t w = 0; w < rows; ++w)
-        out[(size_t)w * pitch + r] = src[w];
+    extern __shared__ uint32_t tr_lds[];
+    const uint32_t stride = rows | 1u;        // odd stride: a row's reads hit distinct banks
+    const uint32_t r0 = blockIdx.x * ENC_G;
+    const uint32_t nr = n_reads - r0 < ENC_G ? n_reads - r0 : ENC_G;
+    const uint32_t total = nr * rows;
+    const uint32_t *src = rowmajor + (size_t)r0 * rows;
+    for (uint32_t g = threadIdx.x; g < total; g += 256u) {
+        const uint32_t rr = (uint32_t)(((uint64_t)g * inv_rows) >> 32);
+        tr_lds[rr * stride + (g - rr * rows)] = __builtin_nontemporal_load(src + g);
+    }
+    __syncthreads();
+    const uint32_t t = threadIdx.x;
+    if (t < nr)
+        for (uint32_t w = 0; w < rows; ++w)
+            out[(size_t)w * pitch + r0 + t] = tr_lds[t * stride + w];
 }
 
 }  // namespace
@@ -147,8 +382,10 @@ hipError_t launch_transpose_reads(const uint32_t *rowmajor, uint32_t n_reads, ui
 {
     if (n_reads == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_transpose_reads, dim3((n_reads + 255) / 256), dim3(256), 0, s, rowmajor,
-                       n_reads, rows, pitch, out);
+    const uint64_t inv_rows = ((1ull << 32) + rows - 1) / rows;
+    hipLaunchKernelGGL(k_transpose_reads, dim3((n_reads + ENC_G - 1) / ENC_G), dim3(256),
+                       (size_t)ENC_G * (rows | 1u) * 4u, s, rowmajor, n_reads, rows, pitch,
+                       inv_rows, out);
     return hipGetLastError();
 }
 
@@ -158,14 +395,26 @@ hipError_t launch_encode_reads(const uint8_t *ascii, const uint64_t *read_off, u
 {
     if (n_reads == 0)
         return hipSuccess;
-    if (layout == GK_READS_SPLIT)
-        hipLaunchKernelGGL(k_encode_reads<GK_READS_SPLIT>, dim3((n_reads + 255) / 256), dim3(256),
-                           0, s, ascii, read_off, n_reads, pitch, rows, packed, len_out,
-                           has_n_out);
+    const bool split = layout == GK_READS_SPLIT;
+    if (((uintptr_t)ascii & 15u) == 0u) {
+        const dim3 grid((n_reads + ENC_G - 1) / ENC_G);
+        const size_t lds = enc_lds_bytes(rows);
+        if (split)
+            hipLaunchKernelGGL(k_encode_reads_staged<GK_READS_SPLIT>, grid, dim3(256), lds, s,
+                               ascii, read_off, n_reads, pitch, rows, packed, len_out, has_n_out);
+        else
+            hipLaunchKernelGGL(k_encode_reads_staged<GK_READS_INTERLEAVED>, grid, dim3(256), lds,
+                               s, ascii, read_off, n_reads, pitch, rows, packed, len_out,
+                               has_n_out);
+        return hipGetLastError();
+    }
+    const dim3 grid((n_reads + 255) / 256);
+    if (split)
+        hipLaunchKernelGGL(k_encode_reads<GK_READS_SPLIT>, grid, dim3(256), 0, s, ascii, read_off,
+                           n_reads, pitch, rows, packed, len_out, has_n_out);
     else
-        hipLaunchKernelGGL(k_encode_reads<GK_READS_INTERLEAVED>, dim3((n_reads + 255) / 256),
-                           dim3(256), 0, s, ascii, read_off, n_reads, pitch, rows, packed,
-                           len_out, has_n_out);
+        hipLaunchKernelGGL(k_encode_reads<GK_READS_INTERLEAVED>, grid, dim3(256), 0, s, ascii,
+                           read_off, n_reads, pitch, rows, packed, len_out, has_n_out);
     return hipGetLastError();
 }
 
