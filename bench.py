@@ -203,6 +203,16 @@ def main() -> int:
     ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--no-verify", action="store_true",
                     help="skip the verification (edit distance) measurement")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="plain: skip the mixed-batch section (config 3)")
+    ap.add_argument("--no-served", action="store_true",
+                    help="plain: skip the served section (config 4)")
+    ap.add_argument("--served-pool", type=int, default=256,
+                    help="plain: pool requests of the served section")
+    ap.add_argument("--served-lambdas", default="2000,3000,4000,5000,6000",
+                    help="plain: arrival rates of the served section")
+    ap.add_argument("--served-duration", type=float, default=5.0,
+                    help="plain: seconds of arrivals per rate of the served section")
     ap.add_argument("--no-calibrate", action="store_true",
                     help="skip the VALU / copy calibration kernels (the roofline then takes "
                          "the spec peak)")
@@ -223,11 +233,12 @@ def main() -> int:
                          "sweep: the plain launch at 100 bp for e = 0..10 and at 150 / 250 bp "
                          "for e = 2, 5, 10 %% of the length")
     ap.add_argument("--lambdas",
-                    default="50,100,200,500,1000,2000,3000,3500,4000,4500,5000,6000,8000",
+                    default="50,100,200,500,1000,2000,3000,3500,4000,4500,5000,6000,7000,8000",
                     help="served: arrival rates (requests/s)")
-    ap.add_argument("--duration", type=float, default=6.0,
+    ap.add_argument("--duration", type=float, default=20.0,
                     help="served: seconds of arrivals per rate and mode")
-    ap.add_argument("--pool", type=int, default=256, help="served: distinct requests")
+    ap.add_argument("--pool", type=int, default=1024,
+                    help="served: distinct requests (each with the oracle's outputs)")
     ap.add_argument("--ref-len", type=int, default=3_100_000_000,
                     help="served: reference length")
     ap.add_argument("--slo-ms", type=float, default=25.0, help="served: p99 target")
@@ -265,7 +276,7 @@ def main() -> int:
     calib = None if args.no_calibrate else measure_peaks(log)
 
     if args.workload == "mixed":
-        return bench_mixed(args, log)
+        return bench_mixed(args, log, calib)
     if args.workload == "served":
         return bench_served(args, log)
     if args.workload == "sweep":
@@ -620,8 +631,24 @@ def main() -> int:
                                              f"1 thread, {dt0 * 1e3:.1f} ms wall"}
         cpu["host_cpu"] = host_cpu_model()
 
+    # The two added rows, measured in the same run: the mixed batch
+    # (persistent launch vs one launch per (length, e) group) and the served
+    # form (batched server vs per-request launches, p50/p99 latency).
+    del dr, dp, batch
+    torch.cuda.empty_cache()
+    mixed = None
+    if not args.no_mixed:
+        mixed = mixed_section(args, log, calib)
+        torch.cuda.empty_cache()
+    served = None
+    if not args.no_served:
+        served = served_section(args, log, args.served_pool,
+                                [float(x) for x in args.served_lambdas.split(",")],
+                                args.served_duration)
+    slo = served["served_at_slo"] if served else None
+
     out = {
-        "metric": "filtered pairs/sec (100bp, e=5) on 1 MI355X, bit-exact",
+        "metric": "filtered pairs/sec (100bp, e=5) on 1 MI355X, bit-exact; p99 request latency",
         "value": round(value, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
@@ -632,12 +659,18 @@ def main() -> int:
                    "pairs_per_step": n_pairs, "read_len": m, "e": e,
                    "read_layout": args.layout, "pairs_per_lane": args.pairs_per_lane},
         "kernel_pairs_per_s": round(n_pairs / k_avg_s, 1),
+        "p99_request_latency_ms": slo["p99_ms"] if slo else None,
+        "p99_at": (f"served form at {slo['lambda']:.0f} requests/s, "
+                   f"{slo['pairs_per_s'] / 1e6:.1f} M pairs/s (the highest rate with p99 <= "
+                   f"{args.slo_ms:g} ms)") if slo else None,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "device_encoded": dev_enc,
         "filter_time": ft,
         "verification": verify,
         "parity": parity,
+        "mixed": mixed,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
     gk.gk_destroy(ctx)
@@ -772,7 +805,7 @@ def bench_sweep(args, log) -> int:
     return 0
 
 
-def bench_mixed(args, log) -> int:
+def mixed_section(args, log, calib=None, n_pairs: int = 1 << 26) -> dict:
     """Mixed batch: 2^26 pairs, read length uniform over {64, 100, 150, 200,
     250, 300}, per-pair e uniform over 0..floor(0.1 m), Zipf(1.5) candidates
     per read.  The persistent launch (gk_filter_mixed, autotuned, replayed
@@ -782,7 +815,6 @@ def bench_mixed(args, log) -> int:
     import gen
     from paper_2103_14978_amd import device, gk
 
-    n_pairs = args.pairs if args.pairs != (1 << 24) else (1 << 26)
     t = time.time()
     ref = gen.c1_reference()
     ps = gen.c3_pairs(ref, n_pairs=n_pairs)
@@ -908,17 +940,14 @@ def bench_mixed(args, log) -> int:
     tuning = [report["tile"], report["ppl"], report["sort_e"], report["blocks_per_cu"]]
     mtraffic = traffic_from_profile(mhash, n_pairs, "k_mixed_w10_config3_counters.json",
                                     tuning=tuning)
+    peak = max(VALU_PEAK_TOPS, calib["valu_measured_Tops"]) if calib else VALU_PEAK_TOPS
     out = {
-        "metric": "filtered pairs/sec, mixed batch (lengths 64-300, per-pair e), 1 MI355X, "
-                  "bit-exact",
-        "value": round(n_pairs * steps / wall_m, 1), "unit": "pairs/s", "n_gpus": 1,
-        "steps": steps, "warmup": warmup, "ms_per_step": round(wall_m * 1e3 / steps, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"mixed batch, {n_pairs} pairs, read length uniform over "
-                               "{64,100,150,200,250,300}, e uniform 0..floor(0.1 m) per pair, "
-                               "Zipf(1.5) candidates per read (<= 1024), 100 Mbp GC-41% "
-                               "reference", "pairs_per_step": n_pairs},
+        "workload": f"mixed batch, {n_pairs} pairs, read length uniform over "
+                    "{64,100,150,200,250,300}, e uniform 0..floor(0.1 m) per pair, "
+                    "Zipf(1.5) candidates per read (<= 1024), 100 Mbp GC-41% reference",
+        "pairs_per_step": n_pairs, "steps": steps, "warmup": warmup,
+        "pairs_per_s": round(n_pairs * steps / wall_m, 1),
+        "ms_per_step": round(wall_m * 1e3 / steps, 4),
         "mixed_kernel_pairs_per_s": round(n_pairs / k_m, 1),
         "grouped": {"launches": len(groups), "pairs_per_s": round(n_pairs * steps / wall_g, 1),
                     "kernel_pairs_per_s": round(n_pairs / k_g, 1),
@@ -927,171 +956,217 @@ def bench_mixed(args, log) -> int:
         "autotune": {k: report.get(k) for k in ("source", "tile", "ppl", "sort_e",
                                                  "blocks_per_cu", "ms")},
         "roofline": {"bound": "alu", "kernel": "k_mixed<10>", "achieved": round(achieved, 3),
-                     "peak": round(VALU_PEAK_TOPS, 3), "unit": "Tops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": mtraffic,
+                     "peak": round(peak, 3), "unit": "Tops/s",
+                     "frac": round(achieved / peak, 4), "traffic": mtraffic,
                      "traffic_GBs": (round(mtraffic / k_m / 1e9, 1) if mtraffic else None),
                      "ops_per_pair_mean": round(ops / n_pairs, 1),
                      "kernel_ms": round(k_m * 1e3, 4), "kernel_source_hash": mhash},
         "parity": parity,
         "verification": vmix,
     }
-    print(json.dumps(out), flush=True)
     gk.gk_destroy(ctx)
+    return out
+
+
+def bench_mixed(args, log, calib=None) -> int:
+    n_pairs = args.pairs if args.pairs != (1 << 24) else (1 << 26)
+    sec = mixed_section(args, log, calib, n_pairs)
+    out = {"metric": "filtered pairs/sec, mixed batch (lengths 64-300, per-pair e), 1 MI355X, "
+                     "bit-exact",
+           "value": sec["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": sec["steps"],
+           "warmup": sec["warmup"], "ms_per_step": sec["ms_per_step"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+           "config": {"workload": sec["workload"], "pairs_per_step": n_pairs}}
+    out.update(sec)
+    print(json.dumps(out), flush=True)
     return 0
 
 
-def bench_served(args, log) -> int:
-    """Served form: a device-resident 3.1 Gbp reference; requests of 10^3 to
-    10^6 pairs (log-uniform), each with one read length in 100..250 and its own
-    e; open-loop Poisson arrivals.  Latency = results in host memory minus the
-    scheduled arrival time, so queueing counts.  The batched server against
-    the sequential per-request form (copy in, launch, copy out, one request at
-    a time on one stream)."""
-    import threading
+class _PoolEntry:
+    pass
+
+
+def loadgen_lib():
+    """libgk_loadgen.so (the native open-loop client) with its ctypes types."""
+    import ctypes
+    from paper_2103_14978_amd import build as hipbuild
+    if not os.path.exists(hipbuild.LOADGEN_LIB):
+        raise ImportError(f"{hipbuild.LOADGEN_LIB} is missing: build the package first")
+    vp, u32, u64, i64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64
+
+    class PoolEntry(ctypes.Structure):
+        _fields_ = [("reads", vp), ("read_off", vp), ("n_reads", u32), ("e", u32),
+                    ("pair_read", vp), ("cand_pos", vp), ("n_pairs", u64),
+                    ("want_accept", vp), ("want_est", vp)]
+
+    class RunArgs(ctypes.Structure):
+        _fields_ = [("srv", vp), ("pool", ctypes.POINTER(PoolEntry)), ("n_pool", u32),
+                    ("n_slots", u32), ("slot_pairs", u64), ("ring_accept", vp),
+                    ("ring_est", vp), ("n_sub", u64), ("arrival_us", vp), ("which", vp),
+                    ("deadline_us", i64), ("t_start_us", i64)]
+    L = ctypes.CDLL(hipbuild.LOADGEN_LIB)
+    L.gkl_run.argtypes = [ctypes.POINTER(RunArgs), vp]
+    L.gkl_run.restype = ctypes.c_int
+    return L, PoolEntry, RunArgs
+
+
+# gkl_sub_result, 64 bytes
+SUB_RESULT = np.dtype([("status", "<i4"), ("submit_status", "<i4"), ("t_arrival_us", "<i8"),
+                       ("t_submit_us", "<i8"), ("t_admit_us", "<i8"), ("t_done_us", "<i8"),
+                       ("n_pairs", "<u8"), ("mismatches", "<u8"), ("checked", "<u4"),
+                       ("slot", "<u4")])
+
+
+def served_section(args, log, pool_size: int, lambdas, duration: float,
+                   warm_s: float = 1.5) -> dict:
+    """Served form (config 4): a device-resident 3.1 Gbp reference; a pool of
+    requests of 10^3 to 10^6 pairs (log-uniform), each with one read length
+    in 100..250 and its own e; open-loop Poisson arrivals submitted by a
+    native client thread (libgk_loadgen).  Latency = results in host memory
+    minus the scheduled arrival, so queueing counts.  Every submission's own
+    output buffer (from a bounded ring, sentinel-filled) is checked against
+    the oracle's outputs for its pool request.  The batched server against
+    the sequential per-request form (copy in, launch, copy out, one request
+    at a time on one stream)."""
+    import ctypes
     import torch
     import gen
+    import oracle
     from paper_2103_14978_amd import gk
 
     t = time.time()
     ref = gen.c4_reference(args.ref_len)
-    log(f"reference {len(ref)} bp generated in {time.time() - t:.1f}s")
+    log(f"served: reference {len(ref)} bp generated in {time.time() - t:.1f}s")
     ctx = gk.gk_create(0)
     t = time.time()
     gk.gk_load_reference(ctx, ref)
-    log(f"reference resident in {time.time() - t:.1f}s")
+    log(f"served: reference resident in {time.time() - t:.1f}s")
     t = time.time()
-    pool = [gen.c4_request(ref, k) for k in range(args.pool)]
+    pool = [gen.c4_request(ref, k) for k in range(pool_size)]
+    pool_pairs = np.array([ps.n_pairs for ps in pool], dtype=np.float64)
+    log(f"served: {len(pool)} requests generated in {time.time() - t:.1f}s, "
+        f"{pool_pairs.sum():.0f} pairs, mean {pool_pairs.mean():.0f}")
+    # The oracle's outputs for every pool request, computed once: every
+    # submission of a request is checked against them.
+    t = time.time()
+    want = [oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read, ps.cand_pos,
+                                ps.meta["e"], n_threads=gen.default_threads()) for ps in pool]
+    oracle_s = time.time() - t
+    log(f"served: oracle outputs of the pool in {oracle_s:.1f}s")
+    del ref
+
     keep = []
 
     def pinned_view(a):
         """a copied into pinned host memory, as a numpy view of it."""
-        t = torch.empty(max(a.nbytes, 1), dtype=torch.uint8, pin_memory=True)
-        keep.append(t)
-        v = t.numpy()[:a.nbytes].view(a.dtype)
+        tt = torch.empty(max(a.nbytes, 1), dtype=torch.uint8, pin_memory=not args.pageable)
+        keep.append(tt)
+        v = tt.numpy()[:a.nbytes].view(a.dtype)
         v[...] = a
         return v
 
-    pool_out = None
-    if not args.pageable:
-        # Requests arrive in pinned buffers (as a server's receive path would
-        # place them), so the copies to the device are plain DMA.  Each pool
-        # request also gets one pinned pair of output arrays, allocated here
-        # once: pinned memory stays bounded (about 1 GB) however far a rate
-        # above the server's capacity lets the backlog grow.  Copies of one
-        # pool request in flight together write the same bytes there.
-        pool_out = []
-        for ps in pool:
-            ps.reads, ps.read_off = pinned_view(ps.reads), pinned_view(ps.read_off)
-            ps.cand_pos, ps.pair_read = pinned_view(ps.cand_pos), pinned_view(ps.pair_read)
-            pool_out.append((pinned_view(np.zeros(ps.n_pairs, np.uint8)),
-                             pinned_view(np.zeros(ps.n_pairs, np.uint16))))
-    pool_pairs = np.array([ps.n_pairs for ps in pool], dtype=np.float64)
-    log(f"{len(pool)} requests generated in {time.time() - t:.1f}s, mean "
-        f"{pool_pairs.mean():.0f} pairs")
-    # Oracle outputs of a few pool requests: every submission of them is checked.
-    import oracle
-    checked = {}
-    for k in range(min(8, len(pool))):
-        ps = pool[k]
-        checked[k] = oracle.filter_batch(ps.reads, ps.read_off, ref, ps.pair_read, ps.cand_pos,
-                                         ps.meta["e"], n_threads=gen.default_threads())
+    L, PoolEntry, RunArgs = loadgen_lib()
+    entries = (PoolEntry * len(pool))()
+    for k, ps in enumerate(pool):
+        ps.reads, ps.read_off = pinned_view(ps.reads), pinned_view(ps.read_off)
+        ps.cand_pos, ps.pair_read = pinned_view(ps.cand_pos), pinned_view(ps.pair_read)
+        ra, rs = np.ascontiguousarray(want[k][0]), np.ascontiguousarray(want[k][1])
+        keep.extend([ra, rs])
+        en = entries[k]
+        en.reads, en.read_off = ps.reads.ctypes.data, ps.read_off.ctypes.data
+        en.n_reads, en.e = ps.n_reads, ps.meta["e"]
+        en.pair_read, en.cand_pos = ps.pair_read.ctypes.data, ps.cand_pos.ctypes.data
+        en.n_pairs = ps.n_pairs
+        en.want_accept, en.want_est = ra.ctypes.data, rs.ctypes.data
+    # Output ring: one buffer per submission in flight (server slots plus a
+    # backlog of as many again), pinned, allocated once.
+    max_slots = 128
+    n_ring = 2 * max_slots
+    slot_pairs = int(pool_pairs.max())
+    ring_acc = pinned_view(np.zeros(n_ring * slot_pairs, np.uint8))
+    ring_est = pinned_view(np.zeros(n_ring * slot_pairs, np.uint16))
     budget = 8 << 30
-    rates = [float(x) for x in args.lambdas.split(",")]
+
+    def run_rate(mode, lam, dur, seed):
+        srv = gk.gk_server_start(ctx, budget, max_slots, 256, mode)
+        rng = np.random.default_rng(seed)
+        n_req = max(20, int(lam * dur))
+        gaps = rng.exponential(1.0 / lam, n_req)
+        which = rng.integers(0, len(pool), n_req).astype(np.uint32)
+        arrivals = (np.cumsum(gaps) * 1e6).astype(np.int64)     # after the start
+        deadline = int(arrivals[-1]) + 10_000_000
+        res = np.zeros(n_req, SUB_RESULT)
+        ra = RunArgs(srv=srv.value, pool=entries, n_pool=len(pool), n_slots=n_ring,
+                     slot_pairs=slot_pairs, ring_accept=ring_acc.ctypes.data,
+                     ring_est=ring_est.ctypes.data, n_sub=n_req,
+                     arrival_us=arrivals.ctypes.data, which=which.ctypes.data,
+                     deadline_us=deadline)
+        st = L.gkl_run(ctypes.byref(ra), res.ctypes.data)
+        t0 = ra.t_start_us
+        ticks = gk.gk_server_tick_log(srv) if mode == gk.GK_SERVER_BATCHED else []
+        n_ticks, per_tick, _ = gk.gk_server_counters(srv)
+        gk.gk_server_stop(srv)       # after this no copy touches the ring
+        if st != 0:
+            raise RuntimeError(f"gkl_run failed: {st}")
+        return res, t0, ticks, n_ticks, per_tick
+
+    def summarise(res, t0, ticks, n_ticks, per_tick, lam, dur):
+        ok = res["status"] == gk.GK_OK
+        lat = (res["t_done_us"][ok] - res["t_arrival_us"][ok]) / 1e3
+        unfinished = int(np.sum(~ok))
+        lat_all = np.concatenate([lat, np.full(unfinished, np.inf)])
+
+        def pct(v, q):
+            x = float(np.percentile(v, q)) if len(v) else float("nan")
+            return round(x, 3) if np.isfinite(x) else None
+        done_pairs = float(np.sum(res["n_pairs"][ok]))
+        end = int(res["t_done_us"][ok].max()) if ok.any() else t0
+        span = max(end - t0, 1) / 1e6
+        rec = {"lambda": lam, "requests": int(len(res)), "unfinished": unfinished,
+               "p50_ms": pct(lat_all, 50), "p99_ms": pct(lat_all, 99),
+               "p999_ms": pct(lat_all, 99.9),
+               "max_ms": round(float(lat.max()), 3) if len(lat) else None,
+               "pairs_per_s": round(done_pairs / span, 1),
+               "checked_submissions": int(np.sum(res["checked"][ok])),
+               "mismatched_submissions": int(np.sum(res["mismatches"] > 0)),
+               "mismatched_pairs": int(np.sum(res["mismatches"])),
+               "submit_lag_p99_ms": pct((res["t_submit_us"][ok] - res["t_arrival_us"][ok])
+                                        / 1e3, 99),
+               "admit_wait_p99_ms": pct((res["t_admit_us"][ok] - res["t_arrival_us"][ok])
+                                        / 1e3, 99),
+               "service_p99_ms": pct((res["t_done_us"][ok] - res["t_admit_us"][ok]) / 1e3, 99),
+               "ticks": n_ticks, "max_requests_per_tick": per_tick}
+        if ticks:
+            tk = np.array([(x.t_launch_us, x.t_kernel_done_us, x.t_done_us, x.n_requests,
+                            x.n_pairs) for x in ticks], dtype=np.int64)
+            rec["tick"] = {"kernel_p50_ms": pct((tk[:, 1] - tk[:, 0]) / 1e3, 50),
+                           "kernel_p99_ms": pct((tk[:, 1] - tk[:, 0]) / 1e3, 99),
+                           "copy_out_p99_ms": pct((tk[:, 2] - tk[:, 1]) / 1e3, 99),
+                           "pairs_p50": pct(tk[:, 4], 50), "pairs_max": int(tk[:, 4].max()),
+                           "requests_p50": pct(tk[:, 3], 50)}
+        return rec
+
     results = {}
-    mismatches = 0
     for mode_name, mode in (("served", gk.GK_SERVER_BATCHED),
                             ("per_request", gk.GK_SERVER_SEQUENTIAL)):
         results[mode_name] = []
         saturated = False
-        # An untimed first round at a moderate rate warms the client side and
-        # the server's first ticks, so the recorded rates measure the
-        # steady state.
-        for lam, warm in [(1000.0, True)] + [(r, False) for r in rates]:
+        # An untimed first round at a moderate rate warms the server's first
+        # ticks and the client, so the recorded rates measure the steady state.
+        run_rate(mode, 1000.0, warm_s, 99 + mode)
+        for lam in lambdas:
             if saturated:
                 results[mode_name].append({"lambda": lam, "skipped": "saturated at a lower rate"})
                 continue
-            srv = gk.gk_server_start(ctx, budget, 128, 256, mode)
-            rng = np.random.default_rng(int(lam) * 7 + mode + (99 if warm else 0))
-            n_req = max(20, int(lam * (1.5 if warm else args.duration)))
-            gaps = rng.exponential(1.0 / lam, n_req)
-            which = rng.integers(0, len(pool), n_req)
-            tickets = []
-            reqs = []
-            done = []
-            lag = []          # submitter lateness: actual submit - scheduled arrival
-            parts = []        # (admission wait, service time) per finished request
-            t0 = gk.gk_clock_us() + 200_000
-            arrivals = t0 + (np.cumsum(gaps) * 1e6).astype(np.int64)
-
-            def submit():
-                for k in range(n_req):
-                    while True:
-                        d = arrivals[k] - gk.gk_clock_us()
-                        if d <= 0:
-                            break
-                        time.sleep(min(d, 2000) / 1e6)
-                    ps = pool[which[k]]
-                    acc, est = pool_out[which[k]] if pool_out is not None else (None, None)
-                    r = gk.Request(ps.reads, ps.read_off, ps.cand_pos, ps.meta["e"],
-                                   pair_read=ps.pair_read, t_arrival_us=int(arrivals[k]),
-                                   accept=acc, est=est)
-                    reqs.append(r)
-                    lag.append(gk.gk_clock_us() - int(arrivals[k]))
-                    tickets.append(gk.gk_server_submit(srv, r))
-
-            th = threading.Thread(target=submit)
-            th.start()
-            deadline = t0 + int((args.duration + 20) * 1e6)
-            k = 0
-            while k < n_req:
-                if k >= len(tickets):
-                    time.sleep(0.0005)
-                    continue
-                left = deadline - gk.gk_clock_us()
-                if left <= 0:
-                    break
-                st, stats = gk.gk_server_wait(srv, tickets[k], left)
-                if st == gk.GK_ETIMEOUT:
-                    break
-                done.append((stats.t_done_us - stats.t_submit_us, stats.n_pairs))
-                parts.append((stats.t_admit_us - stats.t_submit_us,
-                              stats.t_done_us - stats.t_admit_us))
-                w = int(which[k])
-                if w in checked:
-                    ra, rs = checked[w]
-                    mismatches += int(np.sum((reqs[k].accept != ra) | (reqs[k].est != rs)))
-                reqs[k] = None                 # release its output buffers
-                k += 1
-            th.join()
-            # requests still unfinished at the deadline count as missing the SLO
-            unfinished = n_req - len(done)
-            saturated = unfinished > 0
-            ticks, per_tick, _ = gk.gk_server_counters(srv)
-            gk.gk_server_stop(srv)
-            lat = np.array([d for d, _ in done], dtype=np.float64) / 1e3
-            lat_all = np.concatenate([lat, np.full(unfinished, np.inf)])
-            span = (max(arrivals[-1], gk.gk_clock_us()) - t0) / 1e6
-            def pct(q):
-                v = float(np.percentile(lat_all, q))
-                return round(v, 3) if np.isfinite(v) else None
-            rec = {"lambda": lam, "requests": n_req, "unfinished": unfinished,
-                   "p50_ms": pct(50), "p99_ms": pct(99), "p999_ms": pct(99.9),
-                   "max_ms": round(float(lat.max()), 3) if len(lat) else None,
-                   "pairs_per_s": round(float(sum(n for _, n in done)) / span, 1),
-                   "ticks": ticks, "max_requests_per_tick": per_tick,
-                   "submit_lag_p99_ms": round(float(np.percentile(lag, 99)) / 1e3, 3)
-                   if lag else None,
-                   "admit_wait_p99_ms": round(float(np.percentile([a for a, _ in parts], 99))
-                                              / 1e3, 3) if parts else None,
-                   "service_p99_ms": round(float(np.percentile([b for _, b in parts], 99))
-                                           / 1e3, 3) if parts else None}
-            if warm:
-                log(f"{mode_name} warm-up at lambda={lam}: p99 {rec['p99_ms']} ms (not recorded)")
-                saturated = False
-                continue
+            res, t0, ticks, n_ticks, per_tick = run_rate(mode, lam, duration,
+                                                          int(lam) * 7 + mode)
+            rec = summarise(res, t0, ticks, n_ticks, per_tick, lam, duration)
+            saturated = rec["unfinished"] > 0
             results[mode_name].append(rec)
-            log(f"{mode_name} lambda={lam}: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} ms, "
-                f"{rec['pairs_per_s'] / 1e6:.1f} M pairs/s, unfinished {unfinished}")
+            log(f"served {mode_name} lambda={lam}: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} "
+                f"ms, {rec['pairs_per_s'] / 1e6:.1f} M pairs/s, unfinished {rec['unfinished']}, "
+                f"mismatched submissions {rec['mismatched_submissions']} of "
+                f"{rec['checked_submissions']} checked")
 
     def at_slo(rows):
         """The highest rate below the first one that misses the SLO (a later
@@ -1099,33 +1174,50 @@ def bench_served(args, log) -> int:
         best = None
         for r in sorted(rows, key=lambda r: r["lambda"]):
             if ("p99_ms" not in r or r["p99_ms"] is None or r["p99_ms"] > args.slo_ms
-                    or r["unfinished"] != 0):
+                    or r["unfinished"] != 0 or r["mismatched_submissions"] != 0):
                 break
             best = r
         if best is None:
             return None
         return {"lambda": best["lambda"], "pairs_per_s": best["pairs_per_s"],
-                "p99_ms": best["p99_ms"]}
+                "p50_ms": best["p50_ms"], "p99_ms": best["p99_ms"]}
 
     served_slo, seq_slo = at_slo(results["served"]), at_slo(results["per_request"])
+    all_rows = results["served"] + results["per_request"]
     out = {
-        "metric": "p99 request latency and pairs/sec at p99 <= SLO, served filter, 1 MI355X, "
-                  "bit-exact",
-        "value": served_slo["pairs_per_s"] if served_slo else None, "unit": "pairs/s",
-        "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "u32",
-        "vs_baseline": None,
-        "config": {"workload": f"served: {len(ref)} bp GC-41% reference resident, pool of "
-                               f"{len(pool)} requests of 1e3..1e6 pairs (log-uniform, mean "
-                               f"{pool_pairs.mean():.0f}), read length U{{100..250}}, own e "
-                               "U{0..floor(0.1 m)}, open-loop Poisson arrivals, "
-                               f"{args.duration:.0f} s per rate", "slo_p99_ms": args.slo_ms,
-                   "host_memory": "pageable" if args.pageable else "pinned"},
+        "workload": f"served: {args.ref_len} bp GC-41% reference resident, pool of "
+                    f"{len(pool)} requests of 1e3..1e6 pairs (log-uniform, mean "
+                    f"{pool_pairs.mean():.0f}), read length U{{100..250}}, own e "
+                    "U{0..floor(0.1 m)}, open-loop Poisson arrivals from a native client "
+                    f"thread, {duration:.0f} s per rate",
+        "slo_p99_ms": args.slo_ms,
+        "host_memory": "pageable" if args.pageable else "pinned",
         "served_at_slo": served_slo, "per_request_at_slo": seq_slo,
-        "by_rate": results, "parity": {"checked_pool_requests": len(checked),
-                                       "mismatches": mismatches},
+        "speedup_at_slo": (round(served_slo["pairs_per_s"] / seq_slo["pairs_per_s"], 3)
+                           if served_slo and seq_slo else None),
+        "by_rate": results,
+        "parity": {"pool_requests_with_oracle_outputs": len(pool),
+                   "checked_submissions": int(sum(r.get("checked_submissions", 0)
+                                                  for r in all_rows)),
+                   "mismatched_submissions": int(sum(r.get("mismatched_submissions", 0)
+                                                     for r in all_rows)),
+                   "oracle_s": round(oracle_s, 1)},
     }
-    print(json.dumps(out), flush=True)
     gk.gk_destroy(ctx)
+    del keep
+    return out
+
+
+def bench_served(args, log) -> int:
+    lambdas = [float(x) for x in args.lambdas.split(",")]
+    sec = served_section(args, log, args.pool, lambdas, args.duration)
+    out = {"metric": "p99 request latency and pairs/sec at p99 <= SLO, served filter, "
+                     "1 MI355X, bit-exact",
+           "value": sec["served_at_slo"]["pairs_per_s"] if sec["served_at_slo"] else None,
+           "unit": "pairs/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "dtype": "u32", "vs_baseline": None, "config": {"workload": sec["workload"]}}
+    out.update(sec)
+    print(json.dumps(out), flush=True)
     return 0
 
 

@@ -434,6 +434,24 @@ int gk_server_wait(gk_server *srv, uint64_t ticket, int64_t timeout_us,
 int gk_server_counters(gk_server *srv, uint64_t *ticks, uint64_t *max_requests_per_tick,
                        uint64_t *pairs_done);
 
+/* One scheduling tick of a GK_SERVER_BATCHED server, on gk_clock_us()'s
+   clock: when its launch was issued, when the completer saw its kernels
+   finish, and when its requests' results were in host memory. */
+typedef struct gk_tick_record {
+    int64_t  t_launch_us;
+    int64_t  t_kernel_done_us;
+    int64_t  t_done_us;
+    uint32_t n_requests;
+    uint32_t reserved;
+    uint64_t n_pairs;
+} gk_tick_record;
+
+/* The server's tick log: the first min(cap, n) completed ticks in order are
+   copied to out (HOST, cap records; may be NULL when cap is 0), *n_total (may
+   be NULL) receives n, the number recorded (the first 2^20 ticks of the
+   server are kept).  Empty in GK_SERVER_SEQUENTIAL mode. */
+int gk_server_tick_log(gk_server *srv, gk_tick_record *out, uint64_t cap, uint64_t *n_total);
+
 /* Cancel the requests not yet admitted (their status: GK_ECANCELED), finish
    the admitted ones, stop the threads and free the server.  Tickets not yet
    waited for are released. */

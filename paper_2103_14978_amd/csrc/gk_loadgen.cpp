@@ -45,9 +45,12 @@ typedef struct gkl_run_args {
     uint8_t *ring_accept;         // HOST n_slots * slot_pairs
     uint16_t *ring_est;           // HOST n_slots * slot_pairs
     uint64_t n_sub;
-    const int64_t *arrival_us;    // n_sub scheduled arrivals (gk_clock_us), non-decreasing
+    const int64_t *arrival_us;    // n_sub scheduled arrivals, microseconds after the
+                                  // start, non-decreasing
     const uint32_t *which;        // n_sub pool indices
-    int64_t deadline_us;          // no wait extends past this time
+    int64_t deadline_us;          // microseconds after the start: no wait extends past it
+    int64_t t_start_us;           // out: the start on gk_clock_us()'s clock, set 200 ms
+                                  // after the ring is filled with the sentinel
 } gkl_run_args;
 
 // Per submission.  status: the wait's GK_* status, or GKL_UNFINISHED (still
@@ -78,6 +81,13 @@ struct Inflight {
     uint32_t slot;
 };
 
+// Timed wait on the system clock (pthread_cond_timedwait), which the thread
+// sanitizer's interceptors see; waits are bounded by the run's deadline.
+void wait_for_us(std::condition_variable &cv, std::unique_lock<std::mutex> &lk, int64_t us)
+{
+    cv.wait_until(lk, std::chrono::system_clock::now() + std::chrono::microseconds(us));
+}
+
 void fill_sentinel(const gkl_run_args *a, uint32_t slot, uint64_t n)
 {
     std::memset(a->ring_accept + (uint64_t)slot * a->slot_pairs, 0xFF, n);
@@ -91,7 +101,7 @@ extern "C" {
 // Runs the schedule; returns 0, or GK_EINVAL for bad arguments.  The server
 // may still hold buffers of unfinished submissions when this returns: stop
 // the server (gk_server_stop) before the ring is freed.
-int gkl_run(const gkl_run_args *a, gkl_sub_result *res)
+int gkl_run(gkl_run_args *a, gkl_sub_result *res)
 {
     if (!a || !res || !a->srv || !a->pool || a->n_pool == 0 || a->n_slots == 0 ||
         !a->ring_accept || !a->ring_est || (a->n_sub && (!a->arrival_us || !a->which)))
@@ -102,14 +112,17 @@ int gkl_run(const gkl_run_args *a, gkl_sub_result *res)
     for (uint64_t k = 0; k < a->n_sub; ++k)
         if (a->which[k] >= a->n_pool)
             return GK_EINVAL;
+    for (uint32_t s = 0; s < a->n_slots; ++s)
+        fill_sentinel(a, s, a->slot_pairs);
+    const int64_t t0 = gk_clock_us() + 200000;
+    a->t_start_us = t0;
+    const int64_t deadline = t0 + a->deadline_us;
     std::memset(res, 0, a->n_sub * sizeof(gkl_sub_result));
     for (uint64_t k = 0; k < a->n_sub; ++k) {
         res[k].status = GKL_NOT_SUBMITTED;
-        res[k].t_arrival_us = a->arrival_us[k];
+        res[k].t_arrival_us = t0 + a->arrival_us[k];
         res[k].n_pairs = a->pool[a->which[k]].n_pairs;
     }
-    for (uint32_t s = 0; s < a->n_slots; ++s)
-        fill_sentinel(a, s, a->slot_pairs);
 
     std::mutex mu;
     std::condition_variable cv;
@@ -122,12 +135,13 @@ int gkl_run(const gkl_run_args *a, gkl_sub_result *res)
 
     std::thread submitter([&] {
         for (uint64_t k = 0; k < a->n_sub; ++k) {
-            if (a->arrival_us[k] >= a->deadline_us)
+            const int64_t arrival = res[k].t_arrival_us;
+            if (arrival >= deadline)
                 break;
             // Sleep to within 200 us of the arrival (a millisecond at a
             // time, watching for the stop), then spin.
             while (!stop.load()) {
-                const int64_t d = a->arrival_us[k] - gk_clock_us();
+                const int64_t d = arrival - gk_clock_us();
                 if (d <= 0)
                     break;
                 if (d > 300)
@@ -140,10 +154,10 @@ int gkl_run(const gkl_run_args *a, gkl_sub_result *res)
             {
                 std::unique_lock<std::mutex> lk(mu);
                 while (free_slots.empty() && !stop.load()) {
-                    const int64_t left = a->deadline_us - gk_clock_us();
+                    const int64_t left = deadline - gk_clock_us();
                     if (left <= 0)
                         break;
-                    cv.wait_for(lk, std::chrono::microseconds(left));
+                    wait_for_us(cv, lk, left);
                 }
                 if (stop.load() || free_slots.empty())
                     break;
@@ -161,7 +175,7 @@ int gkl_run(const gkl_run_args *a, gkl_sub_result *res)
             r.n_pairs = p.n_pairs;
             r.accept = a->ring_accept + (uint64_t)slot * a->slot_pairs;
             r.est = a->ring_est + (uint64_t)slot * a->slot_pairs;
-            r.t_arrival_us = a->arrival_us[k];
+            r.t_arrival_us = arrival;
             uint64_t ticket = 0;
             res[k].t_submit_us = gk_clock_us();
             res[k].slot = slot;
@@ -187,16 +201,16 @@ int gkl_run(const gkl_run_args *a, gkl_sub_result *res)
         {
             std::unique_lock<std::mutex> lk(mu);
             while (q.empty() && !sub_done) {
-                const int64_t left = a->deadline_us - gk_clock_us();
+                const int64_t left = deadline - gk_clock_us();
                 if (left <= 0)
                     break;
-                cv.wait_for(lk, std::chrono::microseconds(left));
+                wait_for_us(cv, lk, left);
             }
             if (q.empty())
                 break;
             f = q.front();
         }
-        const int64_t left = a->deadline_us - gk_clock_us();
+        const int64_t left = deadline - gk_clock_us();
         if (left <= 0)
             break;
         gk_request_stats st{};

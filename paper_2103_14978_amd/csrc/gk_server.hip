@@ -113,7 +113,11 @@ struct Req {
 struct Tick {
     int buf = 0;
     std::vector<Req *> reqs;
+    int64_t t_launch = 0;
+    uint64_t pairs = 0;
 };
+
+constexpr size_t TICK_LOG_CAP = 1u << 20;   // tick records kept per server
 
 }  // namespace
 
@@ -147,6 +151,7 @@ struct gk_server {
     uint32_t *d_resid = nullptr;
     gkd::MixedArgs margs{};
     uint64_t ticks = 0, tick_req_max = 0, pairs_done = 0;
+    std::vector<gk_tick_record> tick_log;  // first TICK_LOG_CAP ticks, in order
     int tick_buf = 0;
     bool completing = false;               // the completer holds inflight.front()
     // Failure injection for tests of the error paths, with no GPU fault: the
@@ -426,10 +431,13 @@ void scheduler_main(gk_server *s)
             tiles += (uint32_t)((t.reqs[b]->r.n_pairs + s->margs.tile - 1) / s->margs.tile);
         }
         h->prefix[t.reqs.size()] = tiles;
+        for (auto *q : t.reqs)
+            t.pairs += q->r.n_pairs;
         hipError_t e = hipSuccess;
         for (auto *q : t.reqs)
             if (e == hipSuccess)
                 e = hipStreamWaitEvent(s->s_compute, q->ready, 0);
+        t.t_launch = now_us();
         if (e == hipSuccess)
             e = hipGraphLaunch(s->graph[t.buf], s->s_compute);
         if (e == hipSuccess)
@@ -472,6 +480,7 @@ void completer_main(gk_server *s)
         const bool inject = s->fail_tick_at != 0 && ++s->ticks_taken == s->fail_tick_at;
         lk.unlock();
         hipError_t e = hipEventSynchronize(s->tick_done[t.buf]);
+        const int64_t t_kernel_done = now_us();
         const bool released = e == hipSuccess;
         if (released) {
             // The tick's kernels are done with its table: the scheduler may
@@ -490,7 +499,11 @@ void completer_main(gk_server *s)
             e = es;
         if (e == hipSuccess && inject)
             e = hipErrorInvalidValue;
+        const int64_t t_copied = now_us();
         lk.lock();
+        if (e == hipSuccess && s->tick_log.size() < TICK_LOG_CAP)
+            s->tick_log.push_back(gk_tick_record{t.t_launch, t_kernel_done, t_copied,
+                                                 (uint32_t)t.reqs.size(), 0u, t.pairs});
         s->completing = false;
         s->inflight.pop_front();     // fail_all leaves the tick being completed
         for (auto *q : t.reqs)
@@ -735,6 +748,19 @@ int gk_server_counters(gk_server *s, uint64_t *ticks, uint64_t *max_requests_per
         *max_requests_per_tick = s->tick_req_max;
     if (pairs_done)
         *pairs_done = s->pairs_done;
+    return GK_OK;
+}
+
+int gk_server_tick_log(gk_server *s, gk_tick_record *out, uint64_t cap, uint64_t *n_total)
+{
+    if (!s || (cap && !out))
+        return GK_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    const uint64_t n = s->tick_log.size();
+    if (n_total)
+        *n_total = n;
+    if (cap)
+        std::memcpy(out, s->tick_log.data(), (n < cap ? n : cap) * sizeof(gk_tick_record));
     return GK_OK;
 }
 

@@ -110,6 +110,17 @@ class gk_request_stats(ctypes.Structure):
     ]
 
 
+class gk_tick_record(ctypes.Structure):
+    _fields_ = [
+        ("t_launch_us", ctypes.c_int64),
+        ("t_kernel_done_us", ctypes.c_int64),
+        ("t_done_us", ctypes.c_int64),
+        ("n_requests", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+        ("n_pairs", ctypes.c_uint64),
+    ]
+
+
 _lib = None
 
 
@@ -156,6 +167,9 @@ def lib() -> ctypes.CDLL:
         L.gk_server_counters.argtypes = [vp, ctypes.POINTER(u64), ctypes.POINTER(u64),
                                          ctypes.POINTER(u64)]
         L.gk_server_counters.restype = i32
+        L.gk_server_tick_log.argtypes = [vp, ctypes.POINTER(gk_tick_record), u64,
+                                         ctypes.POINTER(u64)]
+        L.gk_server_tick_log.restype = i32
         L.gk_server_stop.argtypes = [vp]
         L.gk_server_stop.restype = i32
         L.gk_clock_us.argtypes = []
@@ -171,9 +185,9 @@ def lib() -> ctypes.CDLL:
 EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
             "gk_load_reference_2bit", "gk_reference_info", "gk_encode_reads", "gk_filter",
             "gk_filter_host", "gk_verify", "gk_set_option",
-            "gk_get_option", "gk_filter_mixed", "gk_tune_mixed", "gk_server_start",
-            "gk_server_submit", "gk_server_wait", "gk_server_counters", "gk_server_stop",
-            "gk_clock_us")
+            "gk_get_option", "gk_filter_mixed", "gk_tune_mixed",
+            "gk_server_start", "gk_server_submit", "gk_server_wait", "gk_server_counters",
+            "gk_server_tick_log", "gk_server_stop", "gk_clock_us")
 
 
 def ptr(x) -> int | None:
@@ -419,6 +433,19 @@ def gk_server_counters(srv) -> tuple[int, int, int]:
     if st != GK_OK:
         raise GkError(st, "gk_server_counters")
     return int(a.value), int(b.value), int(c.value)
+
+
+def gk_server_tick_log(srv):
+    """The server's completed ticks as a list of gk_tick_record."""
+    n = ctypes.c_uint64()
+    st = lib().gk_server_tick_log(srv, None, 0, ctypes.byref(n))
+    if st != GK_OK:
+        raise GkError(st, "gk_server_tick_log")
+    buf = (gk_tick_record * max(1, n.value))()
+    st = lib().gk_server_tick_log(srv, buf, n.value, ctypes.byref(n))
+    if st != GK_OK:
+        raise GkError(st, "gk_server_tick_log")
+    return list(buf[:n.value])
 
 
 def gk_server_stop(srv) -> None:

@@ -18,6 +18,8 @@ STRUCTS = {
     "gk_request": ["reads", "read_off", "n_reads", "e", "pair_read", "cand_pos", "n_pairs",
                    "accept", "est", "t_arrival_us"],
     "gk_request_stats": ["status", "n_pairs", "t_submit_us", "t_admit_us", "t_done_us"],
+    "gk_tick_record": ["t_launch_us", "t_kernel_done_us", "t_done_us", "n_requests",
+                       "reserved", "n_pairs"],
 }
 
 
