@@ -313,6 +313,14 @@ int gk_verify(gk_ctx *ctx, const gk_batch *batch, const uint8_t *accept, uint16_
                                             copied and filtered, so a quarter
                                             of the bytes cross the bus.  Same
                                             results either way.             */
+#define GK_OPT_SERVER_PART_PAIRS    8  /* gk_server_start, batched mode: a
+                                            tick takes at most this many
+                                            pairs of one request (256..2^30,
+                                            default 131072); a larger
+                                            request is spread over ticks    */
+#define GK_OPT_SERVER_TICK_PAIRS    9  /* gk_server_start, batched mode:
+                                            pairs per tick at most
+                                            (4096..2^26, default 2^20)      */
 
 /* Set / get a tuning option.  GK_EINVAL for an unknown option or a value out
    of range. */
@@ -363,15 +371,28 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream, uint64_t sam
  * Serving loop.  Requests of varying size, read length and threshold are
  * submitted from any thread; the server keeps the reference (the context's)
  * and each admitted request's state on the GPU and reports per-request times.
+ * The paper has no server: it filters one batch at a time with one
+ * synchronisation per batch (Sec. 3.5) and sizes its batches from the
+ * device's free memory (Sec. 3.1).  The server generalises both: admission
+ * by a device-memory budget, and batches formed from whatever requests are
+ * loaded when the device is free (every gk_server_* call below belongs to
+ * this addition).
  *
  * GK_SERVER_BATCHED: requests are admitted in arrival order when a slot is
  * free and the device arena (device_budget_bytes, allocated at start) has
  * room for the request's footprint; admitted requests are copied in and
  * encoded on a copy stream while earlier ones are filtered, and every
- * scheduling tick filters all loaded requests together in one persistent
- * launch (the mixed-batch kernel over a table of requests, replayed from a
- * hipGraph), with at most two ticks in flight; results are copied back and the
- * slot and memory freed as each tick completes.
+ * scheduling tick filters parts of the loaded requests together in one
+ * persistent launch (the mixed-batch kernel over a table of parts, replayed
+ * from a hipGraph), with at most two ticks in flight.  A tick takes the
+ * loaded requests in turn, at most GK_OPT_SERVER_PART_PAIRS pairs of each and
+ * at most GK_OPT_SERVER_TICK_PAIRS in all; a request with pairs left waits
+ * for a later tick behind the others, so a large request does not hold back
+ * the small ones loaded after it.  Each part's results are copied back as
+ * its tick completes; a request's slot and memory are freed after its last
+ * part.  The tick's launch uses the context's mixed-batch tuning
+ * (GK_OPT_MIXED_*, e.g. as gk_tune_mixed chose it) and the two server
+ * options as they are when gk_server_start is called.
  * GK_SERVER_SEQUENTIAL: the per-request baseline: one request at a time, copy
  * in, encode, one plain filter launch, copy out, on one stream.
  * Both give the same bytes as gk_filter on the same pairs.
@@ -430,13 +451,14 @@ int gk_server_submit(gk_server *srv, const gk_request *req, uint64_t *ticket);
 int gk_server_wait(gk_server *srv, uint64_t ticket, int64_t timeout_us,
                    gk_request_stats *stats);
 
-/* Ticks launched, most requests in one tick, pairs finished. */
+/* Ticks launched, most request parts in one tick, pairs finished. */
 int gk_server_counters(gk_server *srv, uint64_t *ticks, uint64_t *max_requests_per_tick,
                        uint64_t *pairs_done);
 
 /* One scheduling tick of a GK_SERVER_BATCHED server, on gk_clock_us()'s
    clock: when its launch was issued, when the completer saw its kernels
-   finish, and when its requests' results were in host memory. */
+   finish, and when its parts' results were in host memory; n_requests is
+   the number of request parts in the tick, n_pairs their pairs. */
 typedef struct gk_tick_record {
     int64_t  t_launch_us;
     int64_t  t_kernel_done_us;

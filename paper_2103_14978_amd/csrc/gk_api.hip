@@ -1,5 +1,6 @@
 // Host side of libgk: context, resident reference, argument checks, launches.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -52,7 +53,7 @@ hipError_t finish_reference(gk_ctx *ctx, uint64_t words, uint64_t alloc_words,
                             uint64_t unknown)
 {
     const uint64_t k = gkd::REF_SHIFT_WORDS;
-    hipError_t e = hipMalloc(&ctx->ref_planes_b, alloc_words * sizeof(uint2));
+    hipError_t e = gk_dmalloc(&ctx->ref_planes_b, alloc_words * sizeof(uint2));
     if (e == hipSuccess)
         e = hipMemset(ctx->ref_planes_b + (alloc_words - k), 0, k * sizeof(uint2));
     if (e == hipSuccess)
@@ -60,7 +61,7 @@ hipError_t finish_reference(gk_ctx *ctx, uint64_t words, uint64_t alloc_words,
                       hipMemcpyDeviceToDevice);
     const uint64_t line_words = ((words + gkd::LINE_WORDS - 1) / gkd::LINE_WORDS + 63) / 64 + 1;
     if (e == hipSuccess)
-        e = hipMalloc(&ctx->ref_unk_lines, line_words * sizeof(unsigned long long));
+        e = gk_dmalloc(&ctx->ref_unk_lines, line_words * sizeof(unsigned long long));
     if (e == hipSuccess)
         e = hipMemset(ctx->ref_unk_lines, 0, line_words * sizeof(unsigned long long));
     if (e == hipSuccess && unknown > 0)
@@ -70,9 +71,48 @@ hipError_t finish_reference(gk_ctx *ctx, uint64_t words, uint64_t alloc_words,
     return e;
 }
 
+std::atomic<uint64_t> g_fail_alloc_at{0};   // 0: allocations are never failed
+
+// Whether this allocation is the one gk_detail_fail_alloc asked to fail.
+bool take_injected_failure()
+{
+    uint64_t left = g_fail_alloc_at.load();
+    while (left != 0)
+        if (g_fail_alloc_at.compare_exchange_weak(left, left - 1))
+            return left == 1;
+    return false;
+}
+
 }  // namespace
 
+hipError_t gk_detail_device_alloc(void **p, size_t bytes)
+{
+    if (take_injected_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+hipError_t gk_detail_pinned_alloc(void **p, size_t bytes)
+{
+    if (take_injected_failure()) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
 extern "C" {
+
+// Test hook (not part of the public header): the nth device or pinned-host
+// allocation the library makes from now on, in any context, reports
+// hipErrorOutOfMemory and allocates nothing; 0 cancels a pending one.
+int gk_detail_fail_alloc(uint64_t nth)
+{
+    g_fail_alloc_at.store(nth);
+    return GK_OK;
+}
 
 int gk_create(int device, gk_ctx **out)
 {
@@ -106,7 +146,7 @@ int gk_create(int device, gk_ctx **out)
         g_create_error = "gk_create: cannot read the compute unit count";
         return GK_EDEVICE;
     }
-    e = hipMalloc(&ctx->d_counter, sizeof(unsigned long long));
+    e = gk_dmalloc(&ctx->d_counter, sizeof(unsigned long long));
     if (e != hipSuccess) {
         delete ctx;
         g_create_error = std::string("gk_create: hipMalloc: ") + hipGetErrorName(e);
@@ -163,10 +203,10 @@ int gk_load_reference(gk_ctx *ctx, const char *ascii, uint64_t len)
 
     const uint64_t words = (len + 31) / 32;
     const uint64_t alloc_words = words + gkd::REF_PAD_WORDS;
-    hipError_t e = hipMalloc(&ctx->ref_planes, alloc_words * sizeof(uint2));
+    hipError_t e = gk_dmalloc(&ctx->ref_planes, alloc_words * sizeof(uint2));
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference: hipMalloc planes");
-    e = hipMalloc(&ctx->ref_unk, alloc_words * sizeof(uint32_t));
+    e = gk_dmalloc(&ctx->ref_unk, alloc_words * sizeof(uint32_t));
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference: hipMalloc unknown");
     e = hipMemset(ctx->ref_planes, 0, alloc_words * sizeof(uint2));
@@ -181,7 +221,7 @@ int gk_load_reference(gk_ctx *ctx, const char *ascii, uint64_t len)
     // multiple of 32 and at least 32 (len >= 1), and pack each chunk on the GPU.
     const uint64_t step = std::min<uint64_t>((len + 31) & ~uint64_t(31), 256ull << 20);
     uint8_t *stage = nullptr;
-    e = hipMalloc(&stage, step);
+    e = gk_dmalloc(&stage, step);
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference: hipMalloc staging");
     for (uint64_t first = 0; first < len && e == hipSuccess; first += step) {
@@ -236,10 +276,10 @@ int gk_load_reference_2bit(gk_ctx *ctx, const uint32_t *packed, uint64_t len, ui
 
     const uint64_t words = (len + 31) / 32;
     const uint64_t alloc_words = words + gkd::REF_PAD_WORDS;
-    hipError_t e = hipMalloc(&ctx->ref_planes, alloc_words * sizeof(uint2));
+    hipError_t e = gk_dmalloc(&ctx->ref_planes, alloc_words * sizeof(uint2));
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: hipMalloc planes");
-    e = hipMalloc(&ctx->ref_unk, alloc_words * sizeof(uint32_t));
+    e = gk_dmalloc(&ctx->ref_unk, alloc_words * sizeof(uint32_t));
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: hipMalloc unknown");
     e = hipMemset(ctx->ref_planes, 0, alloc_words * sizeof(uint2));
@@ -254,7 +294,7 @@ int gk_load_reference_2bit(gk_ctx *ctx, const uint32_t *packed, uint64_t len, ui
     // 2^30 bases = 256 MiB of words) and unpack each chunk on the GPU.
     const uint64_t step = std::min<uint64_t>((len + 31) & ~uint64_t(31), 1ull << 30);
     uint32_t *stage = nullptr;
-    e = hipMalloc(&stage, step / 16 * sizeof(uint32_t));
+    e = gk_dmalloc(&stage, step / 16 * sizeof(uint32_t));
     if (e != hipSuccess)
         return free_reference(ctx), hip_fail(ctx, e, "gk_load_reference_2bit: hipMalloc staging");
     for (uint64_t first = 0; first < len && e == hipSuccess; first += step) {
@@ -269,7 +309,7 @@ int gk_load_reference_2bit(gk_ctx *ctx, const uint32_t *packed, uint64_t len, ui
     (void)hipFree(stage);
     uint64_t *d_runs = nullptr;
     if (e == hipSuccess && n_n_runs > 0) {
-        e = hipMalloc(&d_runs, n_n_runs * 2 * sizeof(uint64_t));
+        e = gk_dmalloc(&d_runs, n_n_runs * 2 * sizeof(uint64_t));
         if (e == hipSuccess)
             e = hipMemcpy(d_runs, n_runs, n_n_runs * 2 * sizeof(uint64_t), hipMemcpyHostToDevice);
         if (e == hipSuccess)
@@ -409,7 +449,7 @@ int ensure_mixed_scratch(gk_ctx *ctx, uint64_t n_pairs)
 {
     hipError_t e;
     if (!ctx->d_mixed_counters) {
-        e = hipMalloc(&ctx->d_mixed_counters, 2 * sizeof(uint32_t));
+        e = gk_dmalloc(&ctx->d_mixed_counters, 2 * sizeof(uint32_t));
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_filter_mixed: hipMalloc counters");
     }
@@ -420,7 +460,7 @@ int ensure_mixed_scratch(gk_ctx *ctx, uint64_t n_pairs)
             (void)hipFree(ctx->d_resid);
         ctx->d_resid = nullptr;
         ctx->resid_cap = 0;
-        e = hipMalloc(&ctx->d_resid, need * sizeof(uint32_t));
+        e = gk_dmalloc(&ctx->d_resid, need * sizeof(uint32_t));
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_filter_mixed: hipMalloc residual list");
         ctx->resid_cap = need;
@@ -505,14 +545,14 @@ int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *d
             (void)hipFree(ctx->d_verify_list);
         ctx->d_verify_list = nullptr;
         ctx->verify_cap = 0;
-        hipError_t e = hipMalloc(&ctx->d_verify_list,
+        hipError_t e = gk_dmalloc(&ctx->d_verify_list,
                                  (2 * need + (need + 4095) / 4096) * sizeof(uint32_t));
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_verify: hipMalloc list");
         ctx->verify_cap = need;
     }
     if (!ctx->d_verify_count) {
-        hipError_t e = hipMalloc(&ctx->d_verify_count, 2 * sizeof(uint32_t));
+        hipError_t e = gk_dmalloc(&ctx->d_verify_count, 2 * sizeof(uint32_t));
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_verify: hipMalloc count");
     }
@@ -626,6 +666,16 @@ int gk_set_option(gk_ctx *ctx, int option, int64_t value)
             return fail(ctx, GK_EINVAL, "gk_set_option: host encode threads must be 0..64");
         ctx->host_encode_threads = (uint32_t)value;
         return GK_OK;
+    case GK_OPT_SERVER_PART_PAIRS:
+        if (value < 256 || value > (1ll << 30))
+            return fail(ctx, GK_EINVAL, "gk_set_option: server part pairs must be 256..2^30");
+        ctx->server_part_pairs = (uint64_t)value;
+        return GK_OK;
+    case GK_OPT_SERVER_TICK_PAIRS:
+        if (value < 4096 || value > (1ll << 26))
+            return fail(ctx, GK_EINVAL, "gk_set_option: server tick pairs must be 4096..2^26");
+        ctx->server_tick_pairs = (uint64_t)value;
+        return GK_OK;
     default:
         return fail(ctx, GK_EINVAL, "gk_set_option: unknown option");
     }
@@ -656,6 +706,12 @@ int gk_get_option(const gk_ctx *ctx, int option, int64_t *value)
         return GK_OK;
     case GK_OPT_HOST_ENCODE_THREADS:
         *value = ctx->host_encode_threads;
+        return GK_OK;
+    case GK_OPT_SERVER_PART_PAIRS:
+        *value = (int64_t)ctx->server_part_pairs;
+        return GK_OK;
+    case GK_OPT_SERVER_TICK_PAIRS:
+        *value = (int64_t)ctx->server_tick_pairs;
         return GK_OK;
     default:
         return GK_EINVAL;

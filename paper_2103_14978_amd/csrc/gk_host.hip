@@ -34,7 +34,7 @@ template <typename T>
 hipError_t realloc_device(T *&p, uint64_t count)
 {
     release(p);
-    return hipMalloc(&p, std::max<uint64_t>(count, 1) * sizeof(T));
+    return gk_dmalloc(&p, std::max<uint64_t>(count, 1) * sizeof(T));
 }
 
 // Grows the buffers to the batch (never shrinks them).
@@ -210,7 +210,7 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
             }
             h.stage_cap = 0;
             for (uint8_t *&st : h.stage)
-                if ((e = hipHostMalloc((void **)&st, stage_bytes, hipHostMallocDefault)) !=
+                if ((e = gk_hmalloc((void **)&st, stage_bytes)) !=
                     hipSuccess)
                     return hip_fail(ctx, e, "pinned staging");
             h.stage_cap = stage_bytes;

@@ -61,6 +61,8 @@ struct gk_ctx {
     MixedConfig mixed;
     uint32_t use_graph = 1;                   // GK_OPT_MIXED_GRAPH
     uint32_t host_encode_threads = 0;         // GK_OPT_HOST_ENCODE_THREADS
+    uint64_t server_part_pairs = 1u << 17;    // GK_OPT_SERVER_PART_PAIRS
+    uint64_t server_tick_pairs = 1u << 20;    // GK_OPT_SERVER_TICK_PAIRS
     uint32_t *d_mixed_counters = nullptr;     // [tile counter, residual count]
     uint32_t *d_resid = nullptr;              // residual pair list
     uint64_t resid_cap = 0;
@@ -95,6 +97,30 @@ struct DeviceScope {
             (void)hipSetDevice(prev);
     }
 };
+
+// Every device and pinned-host allocation of the library goes through these
+// two calls, so that gk_detail_fail_alloc can make the n-th one report
+// hipErrorOutOfMemory (and allocate nothing) to test the error paths.
+hipError_t gk_detail_device_alloc(void **p, size_t bytes);
+hipError_t gk_detail_pinned_alloc(void **p, size_t bytes);
+
+template <typename T>
+hipError_t gk_dmalloc(T **p, size_t bytes)
+{
+    void *v = nullptr;
+    const hipError_t e = gk_detail_device_alloc(&v, bytes);
+    *p = static_cast<T *>(v);
+    return e;
+}
+
+template <typename T>
+hipError_t gk_hmalloc(T **p, size_t bytes)
+{
+    void *v = nullptr;
+    const hipError_t e = gk_detail_pinned_alloc(&v, bytes);
+    *p = static_cast<T *>(v);
+    return e;
+}
 
 // Records msg as the context's last error and returns code.
 inline int gk_detail_fail(gk_ctx *ctx, int code, const std::string &msg)

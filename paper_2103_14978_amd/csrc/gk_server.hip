@@ -7,15 +7,20 @@
 //              and the device arena has room, copies the request in on the
 //              copy stream and encodes its reads there (gk_encode_reads'
 //              kernel), then marks it ready;
-//   scheduler  every tick takes all ready requests, fills a batch table in
-//              pinned memory and replays a captured graph on the compute
-//              stream (table copy -> reset -> persistent kernel -> residual
-//              pass); at most two ticks are in flight, the two table buffers
-//              alternate;
-//   completer  waits for ticks in order, copies each request's results back,
-//              frees its arena range and slot, wakes its waiter.
-// So copies of new requests overlap the kernel of the current tick, and a
-// request arriving while others run joins the next tick.
+//   scheduler  every tick takes parts of the ready requests in turn (at most
+//              part_pairs pairs of one request, at most tick_pairs pairs in
+//              all; a request with pairs left goes to the back of the
+//              queue), fills a batch table in pinned memory and replays a
+//              captured graph on the compute stream (table copy -> reset ->
+//              persistent kernel -> residual pass); at most two ticks are in
+//              flight, the two table buffers alternate;
+//   completer  waits for ticks in order, copies each part's results back,
+//              and once a request's last part is back frees its arena range
+//              and slot and wakes its waiter.
+// So copies of new requests overlap the kernel of the current tick, a
+// request arriving while others run joins the next tick, and a large request
+// is spread over several ticks instead of holding one: a small request
+// behind it waits for one tick, not for the large one's whole run.
 //
 // Sequential mode (the per-request baseline): the loader alone takes one
 // request at a time through copy in, encode, one plain gk_filter launch and
@@ -108,11 +113,22 @@ struct Req {
     int64_t t_submit = 0, t_admit = 0, t_done = 0;
     int status = GK_OK;
     bool done = false, admitted = false;
+    // batched mode: pairs [0, next_pair) are in ticks; live_parts of them
+    // are not back yet; failed: a part or the server failed
+    uint64_t next_pair = 0;
+    uint32_t live_parts = 0;
+    bool failed = false;
+};
+
+// Pairs [first, first + n) of one request, filtered in one tick.
+struct Part {
+    Req *q = nullptr;
+    uint64_t first = 0, n = 0;
 };
 
 struct Tick {
     int buf = 0;
-    std::vector<Req *> reqs;
+    std::vector<Part> parts;
     int64_t t_launch = 0;
     uint64_t pairs = 0;
 };
@@ -150,6 +166,7 @@ struct gk_server {
     uint32_t *d_counters = nullptr;
     uint32_t *d_resid = nullptr;
     gkd::MixedArgs margs{};
+    uint64_t part_pairs = 0, tick_pairs = 0;   // batched mode: part and tick bounds
     uint64_t ticks = 0, tick_req_max = 0, pairs_done = 0;
     std::vector<gk_tick_record> tick_log;  // first TICK_LOG_CAP ticks, in order
     int tick_buf = 0;
@@ -211,7 +228,10 @@ void place(gk_server *s, Req *q)
     q->d_est = (uint16_t *)p;
 }
 
-gkd::FilterArgs args_for(const gk_server *s, const Req *q)
+// Arguments of pairs [first, first + n) of a request.  With no pair_read
+// (pair i uses read i) the read arrays are offset too: the transposed rows
+// have stride pitch, so reads + first holds read first + i at column i.
+gkd::FilterArgs args_for(const gk_server *s, const Req *q, uint64_t first, uint64_t n)
 {
     const gk_ctx *c = s->ctx;
     gkd::FilterArgs a{};
@@ -229,12 +249,18 @@ gkd::FilterArgs args_for(const gk_server *s, const Req *q)
     a.reads = q->d_packed;
     a.read_len = q->d_len;
     a.read_has_n = q->d_hasn;
-    a.pair_read = q->d_pr;
-    a.cand_pos = q->d_pos;
+    a.pair_read = q->d_pr ? q->d_pr + first : nullptr;
+    if (!q->d_pr && first > 0) {
+        a.n_reads = first < q->r.n_reads ? (uint32_t)(q->r.n_reads - first) : 0u;
+        a.reads = q->d_packed + first;
+        a.read_len = q->d_len + first;
+        a.read_has_n = q->d_hasn + first;
+    }
+    a.cand_pos = q->d_pos + first;
     a.e_pair = nullptr;
-    a.n_pairs = q->r.n_pairs;
-    a.accept = q->d_acc;
-    a.est = q->d_est;
+    a.n_pairs = n;
+    a.accept = q->d_acc + first;
+    a.est = q->d_est + first;
     a.accept_bits = nullptr;
     a.stream_reads = 0;
     return a;
@@ -261,17 +287,23 @@ hipError_t load_request(gk_server *s, Req *q, hipStream_t st)
     return e;
 }
 
-hipError_t copy_out(Req *q, hipStream_t st)
+// Results of pairs [first, first + n) to the request's host buffers.
+hipError_t copy_out(Req *q, uint64_t first, uint64_t n, hipStream_t st)
 {
-    hipError_t e = hipMemcpyAsync(q->r.accept, q->d_acc, q->r.n_pairs, hipMemcpyDeviceToHost, st);
+    if (n == 0)
+        return hipSuccess;
+    hipError_t e =
+        hipMemcpyAsync(q->r.accept + first, q->d_acc + first, n, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(q->r.est, q->d_est, 2 * q->r.n_pairs, hipMemcpyDeviceToHost, st);
+        e = hipMemcpyAsync(q->r.est + first, q->d_est + first, 2 * n, hipMemcpyDeviceToHost, st);
     return e;
 }
 
 void finish(gk_server *s, Req *q, int status)
 {
     // caller holds s->mu
+    if (q->done)
+        return;
     q->status = status;
     q->t_done = now_us();
     q->done = true;
@@ -281,6 +313,24 @@ void finish(gk_server *s, Req *q, int status)
         q->admitted = false;
     }
     s->pairs_done += q->r.n_pairs;
+}
+
+// Batched mode, caller holds s->mu: a request ends once no part of it is
+// out (so no copy can still touch its host buffers) and either all its pairs
+// are back or it failed.
+void maybe_finish(gk_server *s, Req *q)
+{
+    if (!q->done && q->live_parts == 0 && (q->failed || q->next_pair >= q->r.n_pairs))
+        finish(s, q, q->failed ? GK_EDEVICE : GK_OK);
+}
+
+// A part is back (ok) or abandoned after a failure (!ok); caller holds s->mu.
+void retire(gk_server *s, const Part &p, bool ok)
+{
+    p.q->live_parts--;
+    if (!ok)
+        p.q->failed = true;
+    maybe_finish(s, p.q);
 }
 
 void fail_all(gk_server *s, const std::string &msg)
@@ -294,14 +344,18 @@ void fail_all(gk_server *s, const std::string &msg)
     (void)hipStreamSynchronize(s->s_copy);
     if (s->s_copy2)
         (void)hipStreamSynchronize(s->s_copy2);
+    // Requests with a part in the tick being completed end when the
+    // completer hands that part back.
     for (auto *q : s->pending)
         finish(s, q, GK_EDEVICE);
-    for (auto *q : s->ready)
-        finish(s, q, GK_EDEVICE);
+    for (auto *q : s->ready) {
+        q->failed = true;
+        maybe_finish(s, q);
+    }
     const size_t keep = s->completing && !s->inflight.empty() ? 1 : 0;
     for (size_t i = keep; i < s->inflight.size(); ++i)
-        for (auto *q : s->inflight[i].reqs)
-            finish(s, q, GK_EDEVICE);
+        for (const Part &p : s->inflight[i].parts)
+            retire(s, p, false);
     s->pending.clear();
     s->ready.clear();
     s->inflight.erase(s->inflight.begin() + keep, s->inflight.end());
@@ -356,11 +410,11 @@ void loader_main(gk_server *s)
         if (s->mode == GK_SERVER_SEQUENTIAL) {
             // One request at a time on one stream: copy in, encode, filter, copy out.
             if (e == hipSuccess) {
-                const gkd::FilterArgs a = args_for(s, q);
+                const gkd::FilterArgs a = args_for(s, q, 0, q->r.n_pairs);
                 e = gkd::launch_filter(a, s->wmax, GK_READS_SPLIT, 0, s->s_copy);
             }
             if (e == hipSuccess)
-                e = copy_out(q, s->s_copy);
+                e = copy_out(q, 0, q->r.n_pairs, s->s_copy);
             const hipError_t es = hipStreamSynchronize(s->s_copy);   // always drained
             if (e == hipSuccess)
                 e = es;
@@ -407,36 +461,43 @@ void scheduler_main(gk_server *s)
             break;
         Tick t;
         t.buf = s->tick_buf;
-        // At most 256 requests and 2^20 tiles per tick (launch-wide pair ids
-        // tile * 2048 + slot stay below 2^31).
-        uint64_t tick_tiles = 0;
-        while (!s->ready.empty() && t.reqs.size() < gkd::MAX_TABLE_BATCHES) {
-            const uint64_t nt = (s->ready.front()->r.n_pairs + s->margs.tile - 1) / s->margs.tile;
-            if (!t.reqs.empty() && tick_tiles + nt > (1u << 20))
-                break;
-            tick_tiles += nt;
-            t.reqs.push_back(s->ready.front());
+        // Parts in turn: the front request gives at most part_pairs of its
+        // pairs (fewer when the tick's budget runs out) and, with pairs
+        // left, goes to the back.  At most 256 parts and tick_pairs pairs
+        // (tick_pairs <= 2^26: launch-wide pair ids stay below 2^31).  A
+        // request with no pairs takes one empty part.
+        uint64_t budget = s->tick_pairs;
+        while (!s->ready.empty() && t.parts.size() < gkd::MAX_TABLE_BATCHES && budget > 0) {
+            Req *q = s->ready.front();
             s->ready.pop_front();
+            const uint64_t left = q->r.n_pairs - q->next_pair;
+            const uint64_t take = std::min(left, std::min(s->part_pairs, budget));
+            t.parts.push_back(Part{q, q->next_pair, take});
+            q->next_pair += take;
+            q->live_parts++;
+            budget -= take;
+            t.pairs += take;
+            if (q->next_pair < q->r.n_pairs)
+                s->ready.push_back(q);
         }
         s->buf_busy[t.buf] = true;
         s->tick_buf ^= 1;
         lk.unlock();
 
         gkd::BatchTable *h = s->h_table[t.buf];
-        h->n_batches = (uint32_t)t.reqs.size();
+        h->n_batches = (uint32_t)t.parts.size();
         uint32_t tiles = 0;
-        for (size_t b = 0; b < t.reqs.size(); ++b) {
+        for (size_t b = 0; b < t.parts.size(); ++b) {
+            const Part &p = t.parts[b];
             h->prefix[b] = tiles;
-            h->args[b] = args_for(s, t.reqs[b]);
-            tiles += (uint32_t)((t.reqs[b]->r.n_pairs + s->margs.tile - 1) / s->margs.tile);
+            h->args[b] = args_for(s, p.q, p.first, p.n);
+            tiles += (uint32_t)((p.n + s->margs.tile - 1) / s->margs.tile);
         }
-        h->prefix[t.reqs.size()] = tiles;
-        for (auto *q : t.reqs)
-            t.pairs += q->r.n_pairs;
+        h->prefix[t.parts.size()] = tiles;
         hipError_t e = hipSuccess;
-        for (auto *q : t.reqs)
-            if (e == hipSuccess)
-                e = hipStreamWaitEvent(s->s_compute, q->ready, 0);
+        for (const Part &p : t.parts)
+            if (e == hipSuccess && p.first == 0)   // a request's loads, once
+                e = hipStreamWaitEvent(s->s_compute, p.q->ready, 0);
         t.t_launch = now_us();
         if (e == hipSuccess)
             e = hipGraphLaunch(s->graph[t.buf], s->s_compute);
@@ -450,8 +511,8 @@ void scheduler_main(gk_server *s)
             lk.unlock();
             (void)hipStreamSynchronize(s->s_compute);
             lk.lock();
-            for (auto *q : t.reqs)
-                finish(s, q, GK_EDEVICE);
+            for (const Part &p : t.parts)
+                retire(s, p, false);
             s->buf_busy[t.buf] = false;
             if (e != hipSuccess)
                 fail_all(s, std::string("server tick: ") + hipGetErrorName(e));
@@ -460,8 +521,8 @@ void scheduler_main(gk_server *s)
             break;
         }
         s->ticks++;
-        if (t.reqs.size() > s->tick_req_max)
-            s->tick_req_max = t.reqs.size();
+        if (t.parts.size() > s->tick_req_max)
+            s->tick_req_max = t.parts.size();
         s->inflight.push_back(std::move(t));
         s->cv.notify_all();
     }
@@ -491,9 +552,9 @@ void completer_main(gk_server *s)
             s->cv.notify_all();
             lk.unlock();
         }
-        for (auto *q : t.reqs)
+        for (const Part &p : t.parts)
             if (e == hipSuccess)
-                e = copy_out(q, s->s_d2h);
+                e = copy_out(p.q, p.first, p.n, s->s_d2h);
         const hipError_t es = hipStreamSynchronize(s->s_d2h);     // always drained
         if (e == hipSuccess)
             e = es;
@@ -503,11 +564,11 @@ void completer_main(gk_server *s)
         lk.lock();
         if (e == hipSuccess && s->tick_log.size() < TICK_LOG_CAP)
             s->tick_log.push_back(gk_tick_record{t.t_launch, t_kernel_done, t_copied,
-                                                 (uint32_t)t.reqs.size(), 0u, t.pairs});
+                                                 (uint32_t)t.parts.size(), 0u, t.pairs});
         s->completing = false;
         s->inflight.pop_front();     // fail_all leaves the tick being completed
-        for (auto *q : t.reqs)
-            finish(s, q, e == hipSuccess ? GK_OK : GK_EDEVICE);
+        for (const Part &p : t.parts)
+            retire(s, p, e == hipSuccess);
         if (!released)
             s->buf_busy[t.buf] = false;
         if (e != hipSuccess) {
@@ -584,36 +645,47 @@ int gk_server_start(gk_ctx *ctx, uint64_t device_budget_bytes, uint32_t max_slot
     s->wmax = (max_read_len + 31) / 32;
     s->budget = device_budget_bytes;
     s->arena.init(device_budget_bytes);
-    hipError_t e = hipMalloc(&s->d_arena, device_budget_bytes);
+    hipError_t e = gk_dmalloc(&s->d_arena, device_budget_bytes);
     for (hipStream_t *st : {&s->s_copy, &s->s_copy2, &s->s_compute, &s->s_d2h})
         if (e == hipSuccess)
             e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
     if (e == hipSuccess)
-        e = hipMalloc(&s->d_counters, 2 * sizeof(uint32_t));
+        e = gk_dmalloc(&s->d_counters, 2 * sizeof(uint32_t));
     // Every pair takes at least 11 arena bytes, which bounds a tick's pairs.
     const uint64_t resid_cap = device_budget_bytes / 11 + 1;
     if (e == hipSuccess)
-        e = hipMalloc(&s->d_resid, resid_cap * sizeof(uint32_t));
+        e = gk_dmalloc(&s->d_resid, resid_cap * sizeof(uint32_t));
     if (e == hipSuccess && mode == GK_SERVER_BATCHED) {
+        // The tick's persistent launch takes the context's mixed-batch
+        // tuning (GK_OPT_MIXED_*, as gk_tune_mixed left it) at start.
+        const MixedConfig mc = ctx->mixed;
+        const uint32_t ppl = mc.ppl == 2 && s->wmax <= 10 ? 2u : 1u;
         int per_cu = 0;
-        e = gkd::mixed_blocks_per_cu(s->wmax, GK_READS_SPLIT, 2048, 1, &per_cu);
+        e = gkd::mixed_blocks_per_cu(s->wmax, GK_READS_SPLIT, mc.tile, ppl, &per_cu);
+        if (per_cu < 1)
+            per_cu = 1;
+        const uint32_t bpc = mc.blocks_per_cu && (int)mc.blocks_per_cu < per_cu
+                                 ? mc.blocks_per_cu
+                                 : (uint32_t)per_cu;
+        s->part_pairs = ctx->server_part_pairs;
+        s->tick_pairs = ctx->server_tick_pairs;
         s->margs.table = nullptr;
         s->margs.tile_counter = s->d_counters;
         s->margs.resid_count = s->d_counters + 1;
         s->margs.resid_list = s->d_resid;
         s->margs.n_tiles = 0;
-        s->margs.tile = 2048;
-        s->margs.ppl = 1;
-        s->margs.sort_e = 1;
-        s->margs.blocks = (uint32_t)(per_cu > 0 ? per_cu : 1) * (uint32_t)ctx->cu_count;
+        s->margs.tile = mc.tile;
+        s->margs.ppl = ppl;
+        s->margs.sort_e = mc.sort_e;
+        s->margs.blocks = bpc * (uint32_t)ctx->cu_count;
         s->margs.resid_blocks = 2u * (uint32_t)ctx->cu_count;
         hipStream_t cap = nullptr;
         if (e == hipSuccess)
             e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
         for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-            e = hipHostMalloc(&s->h_table[k], sizeof(gkd::BatchTable), hipHostMallocDefault);
+            e = gk_hmalloc(&s->h_table[k], sizeof(gkd::BatchTable));
             if (e == hipSuccess)
-                e = hipMalloc(&s->d_table[k], sizeof(gkd::BatchTable));
+                e = gk_dmalloc(&s->d_table[k], sizeof(gkd::BatchTable));
             if (e == hipSuccess)
                 e = hipEventCreateWithFlags(&s->tick_done[k], hipEventDisableTiming);
             if (e != hipSuccess)
@@ -694,6 +766,7 @@ int gk_server_submit(gk_server *s, const gk_request *r, uint64_t *ticket)
     q->ticket = s->next_ticket++;
     s->reqs[q->ticket] = q;
     if (r->n_pairs == 0) {
+        q->t_admit = q->t_submit;    // nothing to admit: done at once
         finish(s, q, GK_OK);
     } else {
         s->pending.push_back(q);

@@ -96,6 +96,69 @@ def test_tiny_budget_and_slots_queue(gkctx, served):
         assert_same(a, s, ra, rs, f"tiny budget request {k}")
 
 
+SERVER_DEFAULTS = {gk.GK_OPT_SERVER_PART_PAIRS: 1 << 17, gk.GK_OPT_SERVER_TICK_PAIRS: 1 << 20,
+                   gk.GK_OPT_MIXED_TILE: 4096, gk.GK_OPT_MIXED_PAIRS_PER_LANE: 1,
+                   gk.GK_OPT_MIXED_SORT_E: 1, gk.GK_OPT_MIXED_BLOCKS_PER_CU: 0}
+
+
+def with_options(ctx, opts, fn):
+    for k, v in opts.items():
+        gk.gk_set_option(ctx, k, v)
+    try:
+        return fn()
+    finally:
+        for k in opts:
+            gk.gk_set_option(ctx, k, SERVER_DEFAULTS[k])
+
+
+@pytest.mark.parametrize("part,tick,tile,ppl", [(256, 4096, 2048, 1), (3000, 20_000, 8192, 2),
+                                                (1 << 17, 1 << 20, 4096, 2)])
+def test_requests_split_over_ticks(gkctx, served, part, tick, tile, ppl):
+    """Requests spread over several ticks in parts (one tick holding parts
+    of several requests), under several tick tunings: every request's bytes
+    equal the oracle's."""
+    ref, reqs, want = served
+    gk.gk_load_reference(gkctx, ref)
+    say(f"case: serve split part={part} tick={tick} tile={tile} ppl={ppl}")
+    opts = {gk.GK_OPT_SERVER_PART_PAIRS: part, gk.GK_OPT_SERVER_TICK_PAIRS: tick,
+            gk.GK_OPT_MIXED_TILE: tile, gk.GK_OPT_MIXED_PAIRS_PER_LANE: ppl}
+    outs, (ticks, max_parts, pairs) = with_options(gkctx, opts, lambda: run_server(gkctx, reqs))
+    total = sum(ps.n_pairs for ps, _ in reqs)
+    assert pairs == total
+    assert ticks >= total // tick
+    for k, ((a, s), (ra, rs)) in enumerate(zip(outs, want)):
+        assert_same(a, s, ra, rs, f"split request {k}")
+
+
+def test_split_requests_one_candidate_per_read(gkctx, served):
+    """Requests with no pair_read (pair i uses read i) split into parts: each
+    part's reads are found at the part's offset."""
+    ref = served[0]
+    gk.gk_load_reference(gkctx, ref)
+    reqs = []
+    for k, (n, m, e) in enumerate([(9000, 100, 3), (700, 150, 7), (20_000, 250, 12)]):
+        ps = gen.pairs(ref, seed=777 + k, n_reads=n, lengths=[m], true_frac=0.5,
+                       edit_kind=gen.EDIT_RATE, edit_param=1.2, e_value=e)
+        assert np.array_equal(ps.pair_read, np.arange(n))
+        reqs.append((ps, e))
+    say("case: serve split, one candidate per read")
+    opts = {gk.GK_OPT_SERVER_PART_PAIRS: 1000, gk.GK_OPT_SERVER_TICK_PAIRS: 4096}
+
+    def go():
+        srv = gk.gk_server_start(gkctx, 1 << 28, 16, 256, gk.GK_SERVER_BATCHED)
+        try:
+            objs = [gk.Request(ps.reads, ps.read_off, ps.cand_pos, e) for ps, e in reqs]
+            for t in [gk.gk_server_submit(srv, o) for o in objs]:
+                assert gk.gk_server_wait(srv, t, 60_000_000)[0] == gk.GK_OK
+            return objs
+        finally:
+            gk.gk_server_stop(srv)
+    objs = with_options(gkctx, opts, go)
+    for k, (o, (ps, e)) in enumerate(zip(objs, reqs)):
+        ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, e)
+        assert_same(o.accept, o.est, ra, rs, f"identity request {k}")
+
+
 def test_limits_timeout_and_empty(gkctx, served):
     ref, reqs, want = served
     gk.gk_load_reference(gkctx, ref)
