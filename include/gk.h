@@ -65,6 +65,7 @@ extern "C" {
 #define GK_READS_INTERLEAVED  1u  /* code at bits 2j (low) and 2j+1 (high)   */
 #define GK_MAX_READ_LEN  512u     /* longest read the kernels take           */
 #define GK_MAX_REF_LEN   0xFFFFFFFFull /* positions are 32-bit               */
+#define GK_NOALLOC_MAX_PAIRS 4194304u /* pairs per gk_filter_mixed_noalloc call */
 
 typedef struct gk_ctx gk_ctx;
 
@@ -348,6 +349,28 @@ int gk_get_option(const gk_ctx *ctx, int option, int64_t *value);
  * on stream.
  */
 int gk_filter_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream);
+
+/*
+ * gk_filter_mixed for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same batch rules, tuning (GK_OPT_MIXED_*), launch sequence and results as
+ * gk_filter_mixed, launched directly on stream (no hipGraph; the graph
+ * option is ignored).  It calls no hipMalloc or hipFree and allocates no
+ * stream, event or graph.
+ *
+ * Scratch: the tile counter, the residual count and a residual list of up
+ * to GK_NOALLOC_MAX_PAIRS entries live in one fixed device array of the
+ * library (16 MiB + 256 B), of which every GPU holds its own copy from the
+ * library's load until the process ends; gk_create takes its address on the
+ * context's device.  n_pairs above GK_NOALLOC_MAX_PAIRS returns GK_ERANGE
+ * with nothing launched; n_pairs == 0 returns GK_OK with nothing launched.
+ * Every call on one GPU, from any context and on any stream, uses that GPU's
+ * one array, and the array keeps the last call's contents (the launch
+ * sequence zeroes the counters first): calls that overlap on one GPU race
+ * and give undefined results.  Order them on one stream, or wait for one
+ * before starting the next.  Asynchronous on stream.
+ */
+int gk_filter_mixed_noalloc(gk_ctx *ctx, const gk_batch *batch, void *stream);
 
 /*
  * Autotuner for gk_filter_mixed.  Times every candidate tuning (tile 2048 /

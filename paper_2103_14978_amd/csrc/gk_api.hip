@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <fstream>
+#include <mutex>
 #include <new>
 #include <sstream>
 #include <string>
@@ -71,6 +72,44 @@ hipError_t finish_reference(gk_ctx *ctx, uint64_t words, uint64_t alloc_words,
     return e;
 }
 
+// Scratch of gk_filter_mixed_noalloc: the tile counter and the residual
+// count (words 0 and 1), then, from word NOALLOC_LIST_WORD, the residual
+// list of up to GK_NOALLOC_MAX_PAIRS pair indices.  A file-scope device
+// array, so the entry point allocates nothing; every device holds its own
+// copy until the process ends.  Host code never uses the name itself: its
+// device address is taken once per device (scratch_setup, from gk_create)
+// and kept in g_scratch.
+}  // namespace
+
+namespace gkd {
+constexpr uint32_t NOALLOC_LIST_WORD = 64;
+__device__ __align__(256) uint32_t scratch[NOALLOC_LIST_WORD + GK_NOALLOC_MAX_PAIRS];
+}  // namespace gkd
+
+namespace {
+
+constexpr int MAX_DEVICES = 256;
+std::mutex g_scratch_mu;
+uint32_t *g_scratch[MAX_DEVICES] = {};
+
+// With `device` current: its address of the scratch array, once per device.
+hipError_t scratch_setup(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch[device])
+        return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(gkd::scratch));
+    if (e != hipSuccess)
+        return e;
+    if (!p)
+        return hipErrorInvalidSymbol;
+    g_scratch[device] = static_cast<uint32_t *>(p);
+    return hipSuccess;
+}
+
 std::atomic<uint64_t> g_fail_alloc_at{0};   // 0: allocations are never failed
 
 // Whether this allocation is the one gk_detail_fail_alloc asked to fail.
@@ -81,6 +120,14 @@ bool take_injected_failure()
         if (g_fail_alloc_at.compare_exchange_weak(left, left - 1))
             return left == 1;
     return false;
+}
+
+uint32_t *scratch_of(int device)
+{
+    if (device < 0 || device >= MAX_DEVICES)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch[device];
 }
 
 }  // namespace
@@ -151,6 +198,14 @@ int gk_create(int device, gk_ctx **out)
         delete ctx;
         g_create_error = std::string("gk_create: hipMalloc: ") + hipGetErrorName(e);
         return e == hipErrorOutOfMemory ? GK_ENOMEM : GK_EDEVICE;
+    }
+    e = scratch_setup(device);
+    if (e != hipSuccess) {
+        (void)hipFree(ctx->d_counter);
+        delete ctx;
+        g_create_error = std::string("gk_create: device scratch address: ") +
+                         hipGetErrorName(e);
+        return GK_EDEVICE;
     }
     g_create_error.clear();
     *out = ctx;
@@ -623,6 +678,39 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
     e = hipGraphLaunch(ctx->graph_exec, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "gk_filter_mixed: graph launch");
+    return GK_OK;
+}
+
+int gk_filter_mixed_noalloc(gk_ctx *ctx, const gk_batch *b, void *stream)
+{
+    if (!ctx)
+        return GK_EINVAL;
+    gkd::FilterArgs a{};
+    int st = prepare_batch(ctx, b, "gk_filter_mixed_noalloc", a);
+    if (st != GK_OK)
+        return st == 1 ? GK_OK : st;
+    if (b->n_pairs > GK_NOALLOC_MAX_PAIRS)
+        return fail(ctx, GK_ERANGE,
+                    "gk_filter_mixed_noalloc: n_pairs above GK_NOALLOC_MAX_PAIRS (4194304)");
+    uint32_t *scr = scratch_of(ctx->device);
+    if (!scr)
+        return fail(ctx, GK_EDEVICE, "gk_filter_mixed_noalloc: no scratch address for the device");
+    DeviceGuard g(ctx->device);
+    if (!g.ok)
+        return fail(ctx, GK_EDEVICE, "gk_filter_mixed_noalloc: hipSetDevice failed");
+    a.stream_reads = 0;     // the mixed kernel reads each pair entry twice
+    const uint32_t wmax = (b->max_read_len + 31) / 32;
+    gkd::MixedArgs x{};
+    if ((st = mixed_args(ctx, ctx->mixed, wmax, b->read_layout, x)) != GK_OK)
+        return st;
+    // The same launch sequence as gk_filter_mixed (its first kernel zeroes
+    // the two counters), on the library's scratch array and without a graph.
+    x.tile_counter = scr;
+    x.resid_count = scr + 1;
+    x.resid_list = scr + gkd::NOALLOC_LIST_WORD;
+    const hipError_t e = gkd::launch_mixed(a, x, wmax, b->read_layout, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "gk_filter_mixed_noalloc: launch");
     return GK_OK;
 }
 

@@ -25,6 +25,7 @@ GK_VERIFY_MAX_E = 31
 GK_FLAG_NO_REFINE = 1
 GK_FLAG_HAMMING_FASTPATH = 2
 GK_MAX_READ_LEN = 512
+GK_NOALLOC_MAX_PAIRS = 1 << 22
 GK_READS_SPLIT, GK_READS_INTERLEAVED = 0, 1
 GK_OPT_PAIRS_PER_LANE = 1
 GK_OPT_MIXED_TILE = 2
@@ -157,6 +158,8 @@ def lib() -> ctypes.CDLL:
         L.gk_verify.restype = i32
         L.gk_filter_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
         L.gk_filter_mixed.restype = i32
+        L.gk_filter_mixed_noalloc.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
+        L.gk_filter_mixed_noalloc.restype = i32
         L.gk_tune_mixed.argtypes = [vp, ctypes.POINTER(gk_batch), vp, u64, ctypes.c_char_p,
                                     ctypes.c_char_p, ctypes.c_size_t]
         L.gk_tune_mixed.restype = i32
@@ -187,7 +190,7 @@ def lib() -> ctypes.CDLL:
 EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
             "gk_load_reference_2bit", "gk_reference_info", "gk_encode_reads", "gk_filter",
             "gk_filter_host", "gk_verify", "gk_set_option",
-            "gk_get_option", "gk_filter_mixed", "gk_tune_mixed",
+            "gk_get_option", "gk_filter_mixed", "gk_filter_mixed_noalloc", "gk_tune_mixed",
             "gk_server_start", "gk_server_submit", "gk_server_wait", "gk_server_counters",
             "gk_server_tick_log", "gk_server_stop", "gk_clock_us")
 
@@ -357,6 +360,11 @@ def gk_verify(ctx, batch: gk_batch, accept, dist, stream=None) -> None:
 def gk_filter_mixed(ctx, batch: gk_batch, stream=None) -> None:
     _check(ctx, lib().gk_filter_mixed(ctx, ctypes.byref(batch), stream_handle(stream)),
            "gk_filter_mixed")
+
+
+def gk_filter_mixed_noalloc(ctx, batch: gk_batch, stream=None) -> None:
+    _check(ctx, lib().gk_filter_mixed_noalloc(ctx, ctypes.byref(batch), stream_handle(stream)),
+           "gk_filter_mixed_noalloc")
 
 
 def gk_tune_mixed(ctx, batch: gk_batch, stream=None, sample_pairs: int = 0,

@@ -61,7 +61,8 @@ def test_constants_match_header():
     from paper_2103_14978_amd import gk
     hdr = open(os.path.join(ROOT, "include", "gk.h")).read()
     for name in ("GK_FLAG_NO_REFINE", "GK_FLAG_HAMMING_FASTPATH", "GK_VERIFY_MAX_E",
-                 "GK_MAX_READ_LEN", "GK_READS_SPLIT", "GK_READS_INTERLEAVED"):
+                 "GK_MAX_READ_LEN", "GK_READS_SPLIT", "GK_READS_INTERLEAVED",
+                 "GK_NOALLOC_MAX_PAIRS"):
         m = re.search(rf"#define\s+{name}\s+(\w+)", hdr)
         assert m, name
         assert int(m.group(1).rstrip("uU").rstrip("uU"), 0) == getattr(gk, name), name
