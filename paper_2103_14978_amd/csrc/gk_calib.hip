@@ -12,6 +12,13 @@
 //   kind 2  v_xor_b32       (2-input logic: the comparisons)
 //   kind 3  v_and_or_b32    (3-input logic)
 //   kind 4  v_or3_b32       (3-input logic)
+//   kind 5  v_bitop3_b32    (any 3-input logic function; here xor3)
+//   kind 6  v_and_b32       (2-input logic, 32-bit VOP2 encoding)
+//   kind 7  v_lshlrev_b32   (shift, VOP2 encoding)
+//   kind 8  v_xor_b32_e64   (2-input logic in the 64-bit VOP3 encoding)
+//   kind 9  v_add_u32       (32-bit add, VOP2 encoding)
+//   kind 10 v_perm_b32      (byte permute, 3 inputs)
+//   kind 11 v_bcnt_u32_b32  (population count, VOP3 encoding)
 // Lane-ops/s = workgroups * 256 * iterations * 64 / kernel time.
 #include <hip/hip_runtime.h>
 
@@ -33,8 +40,22 @@ __device__ __forceinline__ void step(uint32_t &x, uint32_t y, uint32_t z)
         GKC_STEP2("v_xor_b32", x, y);
     else if (KIND == 3)
         GKC_STEP3("v_and_or_b32", x, y, z);
-    else
+    else if (KIND == 4)
         GKC_STEP3("v_or3_b32", x, y, z);
+    else if (KIND == 5)
+        asm volatile("v_bitop3_b32 %0, %1, %2, %0 bitop3:0x96" : "+v"(x) : "v"(y), "v"(z));
+    else if (KIND == 6)
+        GKC_STEP2("v_and_b32", x, y);
+    else if (KIND == 7)
+        GKC_STEP2("v_lshlrev_b32", x, y);
+    else if (KIND == 8)
+        GKC_STEP2("v_xor_b32_e64", x, y);
+    else if (KIND == 9)
+        GKC_STEP2("v_add_u32", x, y);
+    else if (KIND == 10)
+        GKC_STEP3("v_perm_b32", x, y, z);
+    else
+        GKC_STEP2("v_bcnt_u32_b32", x, y);
 }
 
 template <int KIND>
@@ -89,8 +110,22 @@ hipError_t launch_kind(int kind, uint32_t blocks, uint32_t iters, uint32_t *sink
         return launch_valu<2>(blocks, iters, sink, s);
     case 3:
         return launch_valu<3>(blocks, iters, sink, s);
-    default:
+    case 4:
         return launch_valu<4>(blocks, iters, sink, s);
+    case 5:
+        return launch_valu<5>(blocks, iters, sink, s);
+    case 6:
+        return launch_valu<6>(blocks, iters, sink, s);
+    case 7:
+        return launch_valu<7>(blocks, iters, sink, s);
+    case 8:
+        return launch_valu<8>(blocks, iters, sink, s);
+    case 9:
+        return launch_valu<9>(blocks, iters, sink, s);
+    case 10:
+        return launch_valu<10>(blocks, iters, sink, s);
+    default:
+        return launch_valu<11>(blocks, iters, sink, s);
     }
 }
 
@@ -98,7 +133,7 @@ hipError_t launch_kind(int kind, uint32_t blocks, uint32_t iters, uint32_t *sink
 
 extern "C" {
 
-// Issue rate of VALU instruction `kind` (0..4, above) on the current device:
+// Issue rate of VALU instruction `kind` (0..11, above) on the current device:
 // lane-ops per second over `reps` timed launches (after one warm-up), each of
 // blocks_per_cu * CUs workgroups running `iters` loop iterations.  *best_ms:
 // the fastest launch, from which *lane_ops_per_s is computed.  Returns 0, or
@@ -106,7 +141,7 @@ extern "C" {
 int gkc_valu_rate(int kind, uint32_t blocks_per_cu, uint32_t iters, uint32_t reps,
                   double *lane_ops_per_s, double *best_ms)
 {
-    if (kind < 0 || kind > 4 || blocks_per_cu < 1 || iters < 1 || reps < 1 || !lane_ops_per_s ||
+    if (kind < 0 || kind > 11 || blocks_per_cu < 1 || iters < 1 || reps < 1 || !lane_ops_per_s ||
         !best_ms)
         return -1;
     int dev = 0, cus = 0;
