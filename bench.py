@@ -57,10 +57,10 @@ def kernel_source_hash(files=("gk_filter.hip", "gk_pair.h", "gk_args.h")) -> str
 
 def traffic_from_profile(kernel_hash: str, n_pairs: int,
                          name: str = "k_filter_w4_config1_e5_counters.json", kernel=None,
-                         tuning=None):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on this exact kernel source, batch size, kernel and tuning; else
-    None."""
+                         tuning=None, field: str = "hbm_bytes_per_launch"):
+    """HBM bytes per launch (or another per-launch field) from the committed
+    counter summary, if it was taken on this exact kernel source, batch size,
+    kernel and tuning; else None."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
@@ -73,7 +73,7 @@ def traffic_from_profile(kernel_hash: str, n_pairs: int,
         return None
     if tuning is not None and d.get("tuning") != tuning:
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d.get(field)
 
 
 def host_encode_fixed(reads, n_reads: int, m: int, rows: int, chunk: int = 1 << 20):
@@ -123,11 +123,34 @@ def plain_kernel_name(words: int, e: int, pairs_per_lane: int) -> str:
     return f"k_filter_single<{words}" if pairs_per_lane == 1 else f"k_filter<{words}"
 
 
+# VALU instruction kinds timed by the calibration kernels of libgk_calib.so
+# (kind number -> name).
+CALIB_KINDS = {0: "v_bfi_b32", 1: "v_alignbit_b32", 2: "v_xor_b32", 3: "v_and_or_b32",
+               4: "v_or3_b32", 5: "v_bitop3_b32", 6: "v_and_b32", 7: "v_lshlrev_b32",
+               8: "v_xor_b32_e64", 9: "v_add_u32", 10: "v_perm_b32", 11: "v_bcnt_u32_b32"}
+
+# The VALU instructions of the filter's per-mask loops (the deletion and
+# insertion loops of the fast path, 96 instructions per pass of both), by the
+# calibrated kind each issues like, from the gfx950 assembly of
+# k_filter_single<4>: funnel shifts, three-input logic, two-input logic,
+# shifts (left and right), and-or / or3, and two compares (taken at the
+# and-or rate).
+FILTER_LOOP_MIX = {"v_alignbit_b32": 37, "v_bitop3_b32": 26, "v_xor_b32": 9, "v_and_b32": 3,
+                   "v_lshlrev_b32": 13, "v_and_or_b32": 7, "v_or3_b32": 1}
+
+
+def mix_peak(rates: dict, mix: dict = FILTER_LOOP_MIX) -> float:
+    """Issue ceiling (lane-ops/s) of an instruction stream holding mix[k]
+    instructions of each kind k, each issuing at its measured rate."""
+    return sum(mix.values()) / sum(n / rates[k] for k, n in mix.items())
+
+
 def measure_peaks(log):
-    """The device's measured VALU issue rate for the instruction kinds the
-    filter is made of (3-input bit select, funnel shift, 2-input XOR, and-or,
-    or3), in lane-ops/s, and its device copy rate, from the calibration
-    kernels of libgk_calib.so.  The roofline takes max(spec, measured)."""
+    """The device's measured VALU issue rate, per instruction kind (8
+    independent chains per lane, all CUs), and its device copy rate, from
+    the calibration kernels of libgk_calib.so.  The filter's ceiling is the
+    issue rate of its own instruction mix (mix_peak); the roofline takes
+    max(spec, that)."""
     import ctypes
     from paper_2103_14978_amd import build as hipbuild
     if not os.path.exists(hipbuild.CALIB_LIB):
@@ -138,10 +161,8 @@ def measure_peaks(log):
                                 ctypes.POINTER(d), ctypes.POINTER(d)]
     L.gkc_copy_rate.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.POINTER(d),
                                 ctypes.POINTER(d)]
-    kinds = {0: "v_bfi_b32", 1: "v_alignbit_b32", 2: "v_xor_b32", 3: "v_and_or_b32",
-             4: "v_or3_b32"}
     valu = {}
-    for k, name in kinds.items():
+    for k, name in CALIB_KINDS.items():
         rate, ms = d(), d()
         st = L.gkc_valu_rate(k, 8, 4096, 3, ctypes.byref(rate), ctypes.byref(ms))
         if st != 0:
@@ -151,12 +172,22 @@ def measure_peaks(log):
     st = L.gkc_copy_rate(2 << 30, 5, ctypes.byref(rate), ctypes.byref(ms))
     if st != 0:
         raise RuntimeError(f"gkc_copy_rate failed: {st}")
-    out = {"valu_Tops": valu, "valu_measured_Tops": max(valu.values()),
+    out = {"valu_Tops": valu,
+           "filter_mix_Tops": round(mix_peak(valu), 3),
+           "filter_loop_mix": FILTER_LOOP_MIX,
            "copy_GBs": round(rate.value / 1e9, 1),
            "what": "8 independent chains per lane of one instruction kind, 8 workgroups of "
-                   "256 lanes per CU, best of 3; copy: 2 GiB read + 2 GiB written, best of 5"}
-    log(f"calibration: VALU {valu} T lane-ops/s; copy {out['copy_GBs']} GB/s")
+                   "256 lanes per CU, best of 3; filter_mix: the issue ceiling of the filter's "
+                   "per-mask loops, each instruction at the measured rate of its kind; copy: "
+                   "2 GiB read + 2 GiB written, best of 5"}
+    log(f"calibration: VALU {valu} T lane-ops/s; filter mix {out['filter_mix_Tops']} T; "
+        f"copy {out['copy_GBs']} GB/s")
     return out
+
+
+def valu_peak(calib) -> float:
+    """The VALU roof: max(spec, the measured ceiling of the filter's mix)."""
+    return max(VALU_PEAK_TOPS, calib["filter_mix_Tops"]) if calib else VALU_PEAK_TOPS
 
 
 def events_ms(fn, k: int, stream, warm: int = 2, stats: bool = False):
@@ -573,12 +604,19 @@ def main() -> int:
     khash = kernel_source_hash()
     kname = plain_kernel_name((m + 31) // 32, e, args.pairs_per_lane)
     traffic = traffic_from_profile(khash, n_pairs, kernel=kname)
-    peak = max(VALU_PEAK_TOPS, calib["valu_measured_Tops"]) if calib else VALU_PEAK_TOPS
+    valu_insts = traffic_from_profile(khash, n_pairs, kernel=kname,
+                                      field="valu_insts_per_launch")
+    peak = valu_peak(calib)
+    # issued: the VALU instructions the counters saw per launch (x 64 lanes)
+    # over the mean kernel time, against the same roof
+    issued_tops = valu_insts * 64 / k_avg_s / 1e12 if valu_insts else None
     roofline = {"bound": "alu", "kernel": kname + ">", "achieved": round(achieved_tops, 3),
                 "peak": round(peak, 3), "unit": "Tops/s",
                 "frac": round(achieved_tops / peak, 4), "traffic": traffic,
+                "issued": round(issued_tops, 3) if issued_tops else None,
+                "issued_frac": round(issued_tops / peak, 4) if issued_tops else None,
                 "peak_spec": round(VALU_PEAK_TOPS, 3),
-                "peak_measured": calib["valu_measured_Tops"] if calib else None,
+                "peak_measured": calib["filter_mix_Tops"] if calib else None,
                 "calibration": calib,
                 "traffic_GBs": (round(traffic / k_avg_s / 1e9, 1) if traffic else None),
                 "ops_per_pair": ops_per_pair(m, e), "kernel_ms": round(k_avg_s * 1e3, 4),
@@ -940,7 +978,7 @@ def mixed_section(args, log, calib=None, n_pairs: int = 1 << 26) -> dict:
     tuning = [report["tile"], report["ppl"], report["sort_e"], report["blocks_per_cu"]]
     mtraffic = traffic_from_profile(mhash, n_pairs, "k_mixed_w10_config3_counters.json",
                                     tuning=tuning)
-    peak = max(VALU_PEAK_TOPS, calib["valu_measured_Tops"]) if calib else VALU_PEAK_TOPS
+    peak = valu_peak(calib)
     out = {
         "workload": f"mixed batch, {n_pairs} pairs, read length uniform over "
                     "{64,100,150,200,250,300}, e uniform 0..floor(0.1 m) per pair, "
@@ -1018,7 +1056,7 @@ SUB_RESULT = np.dtype([("status", "<i4"), ("submit_status", "<i4"), ("t_arrival_
 
 
 def served_section(args, log, pool_size: int, lambdas, duration: float,
-                   warm_s: float = 1.5) -> dict:
+                   warm_s: float = 1.5, lead: float = 0.5) -> dict:
     """Served form (config 4): a device-resident 3.1 Gbp reference; a pool of
     requests of 10^3 to 10^6 pairs (log-uniform), each with one read length
     in 100..250 and its own e; open-loop Poisson arrivals submitted by a
@@ -1087,10 +1125,13 @@ def served_section(args, log, pool_size: int, lambdas, duration: float,
     ring_est = pinned_view(np.zeros(n_ring * slot_pairs, np.uint16))
     budget = 8 << 30
 
-    def run_rate(mode, lam, dur, seed):
+    def run_rate(mode, lam, dur, seed, lead=0.0):
+        """lead + dur seconds of arrivals at lam on a fresh server; the first
+        lead seconds warm it (their submissions are left out of the
+        figures)."""
         srv = gk.gk_server_start(ctx, budget, max_slots, 256, mode)
         rng = np.random.default_rng(seed)
-        n_req = max(20, int(lam * dur))
+        n_req = max(20, int(lam * (dur + lead)))
         gaps = rng.exponential(1.0 / lam, n_req)
         which = rng.integers(0, len(pool), n_req).astype(np.uint32)
         arrivals = (np.cumsum(gaps) * 1e6).astype(np.int64)     # after the start
@@ -1110,7 +1151,14 @@ def served_section(args, log, pool_size: int, lambdas, duration: float,
             raise RuntimeError(f"gkl_run failed: {st}")
         return res, t0, ticks, n_ticks, per_tick
 
-    def summarise(res, t0, ticks, n_ticks, per_tick, lam, dur):
+    def summarise(res, t0, ticks, n_ticks, per_tick, lam, dur, lead=0.0):
+        # only the submissions (and ticks) after the warm-up lead
+        t0 = t0 + int(lead * 1e6)
+        res = res[res["t_arrival_us"] >= t0]
+        if ticks:
+            ticks = [x for x in ticks if x.t_launch_us >= t0]
+            n_ticks = len(ticks)
+            per_tick = max((x.n_requests for x in ticks), default=0)
         ok = res["status"] == gk.GK_OK
         lat = (res["t_done_us"][ok] - res["t_arrival_us"][ok]) / 1e3
         unfinished = int(np.sum(~ok))
@@ -1139,11 +1187,44 @@ def served_section(args, log, pool_size: int, lambdas, duration: float,
         if ticks:
             tk = np.array([(x.t_launch_us, x.t_kernel_done_us, x.t_done_us, x.n_requests,
                             x.n_pairs) for x in ticks], dtype=np.int64)
-            rec["tick"] = {"kernel_p50_ms": pct((tk[:, 1] - tk[:, 0]) / 1e3, 50),
-                           "kernel_p99_ms": pct((tk[:, 1] - tk[:, 0]) / 1e3, 99),
+            kern = (tk[:, 1] - tk[:, 0]) / 1e3
+            gaps = np.diff(tk[:, 0]) / 1e3 if len(tk) > 1 else np.zeros(1)
+            rec["tick"] = {"kernel_p50_ms": pct(kern, 50),
+                           "kernel_p99_ms": pct(kern, 99),
+                           "kernel_max_ms": round(float(kern.max()), 3),
                            "copy_out_p99_ms": pct((tk[:, 2] - tk[:, 1]) / 1e3, 99),
+                           "copy_out_max_ms": round(float((tk[:, 2] - tk[:, 1]).max() / 1e3), 3),
+                           "launch_gap_max_ms": round(float(gaps.max()), 3),
                            "pairs_p50": pct(tk[:, 4], 50), "pairs_max": int(tk[:, 4].max()),
-                           "requests_p50": pct(tk[:, 3], 50)}
+                           "requests_p50": pct(tk[:, 3], 50),
+                           # the first ticks: launch (ms after the timed
+                           # start), kernel ms, pairs
+                           "first": [[round((int(x[0]) - t0) / 1e3, 2),
+                                      round((int(x[1]) - int(x[0])) / 1e3, 3), int(x[4])]
+                                     for x in tk[:12]]}
+        # The slowest submissions: where their time went, and what the
+        # server's ticks did while the slowest one was in service.
+        if ok.any():
+            idx = np.nonzero(ok)[0]
+            order = idx[np.argsort(lat)[::-1][:8]]
+            rec["slowest"] = [
+                {"arrival_ms": round((int(res["t_arrival_us"][i]) - t0) / 1e3, 3),
+                 "latency_ms": round((int(res["t_done_us"][i]) - int(res["t_arrival_us"][i]))
+                                     / 1e3, 3),
+                 "admit_wait_ms": round((int(res["t_admit_us"][i]) -
+                                         int(res["t_arrival_us"][i])) / 1e3, 3),
+                 "n_pairs": int(res["n_pairs"][i])} for i in order]
+            if ticks:
+                i = order[0]
+                a0, a1 = int(res["t_admit_us"][i]), int(res["t_done_us"][i])
+                win = (tk[:, 0] >= a0) & (tk[:, 0] <= a1)
+                if win.any():
+                    w = tk[win]
+                    rec["slowest_window"] = {
+                        "ticks": int(win.sum()), "pairs": int(w[:, 4].sum()),
+                        "parts": int(w[:, 3].sum()),
+                        "kernel_max_ms": round(float((w[:, 1] - w[:, 0]).max() / 1e3), 3),
+                        "copy_out_max_ms": round(float((w[:, 2] - w[:, 1]).max() / 1e3), 3)}
         return rec
 
     results = {}
@@ -1159,8 +1240,8 @@ def served_section(args, log, pool_size: int, lambdas, duration: float,
                 results[mode_name].append({"lambda": lam, "skipped": "saturated at a lower rate"})
                 continue
             res, t0, ticks, n_ticks, per_tick = run_rate(mode, lam, duration,
-                                                          int(lam) * 7 + mode)
-            rec = summarise(res, t0, ticks, n_ticks, per_tick, lam, duration)
+                                                          int(lam) * 7 + mode, lead)
+            rec = summarise(res, t0, ticks, n_ticks, per_tick, lam, duration, lead)
             saturated = rec["unfinished"] > 0
             results[mode_name].append(rec)
             log(f"served {mode_name} lambda={lam}: p50 {rec['p50_ms']} ms, p99 {rec['p99_ms']} "
@@ -1189,7 +1270,8 @@ def served_section(args, log, pool_size: int, lambdas, duration: float,
                     f"{len(pool)} requests of 1e3..1e6 pairs (log-uniform, mean "
                     f"{pool_pairs.mean():.0f}), read length U{{100..250}}, own e "
                     "U{0..floor(0.1 m)}, open-loop Poisson arrivals from a native client "
-                    f"thread, {duration:.0f} s per rate",
+                    f"thread, {duration:.0f} s per rate after {lead:g} s of arrivals at that "
+                    "rate that warm the fresh server",
         "slo_p99_ms": args.slo_ms,
         "host_memory": "pageable" if args.pageable else "pinned",
         "served_at_slo": served_slo, "per_request_at_slo": seq_slo,

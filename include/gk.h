@@ -339,14 +339,20 @@ int gk_get_option(const gk_ctx *ctx, int option, int64_t *value);
  * path for its read length; pairs with more than 31 shifts are finished by a
  * general-path pass; accept bits (if requested) by a pass over the accept
  * codes.  The launch sequence is captured in a hipGraph the first time a
- * given batch description and tuning are seen and replayed after that
- * (GK_OPT_MIXED_GRAPH).  Results are identical to gk_filter's.
+ * given shape (words per mask, read layout) and tuning are seen and replayed
+ * after that (GK_OPT_MIXED_GRAPH): the batch's arguments reach the graph
+ * through a device table that a copy on the stream fills before each replay,
+ * so every batch of that shape replays the same graph.  Batches of more than
+ * 2^30 pairs, and batches with variant flags, are launched directly.
+ * Results are identical to gk_filter's.
  *
  * Same batch rules and errors as gk_filter.  The context keeps scratch for
- * it: two counters and a residual list of min(n_pairs, 2^30) entries (grown
- * on demand, kept until gk_destroy).  Calls that overlap on one context race
- * on that scratch: one gk_filter_mixed at a time per context.  Asynchronous
- * on stream.
+ * it: two counters, a residual list of min(n_pairs, 2^30) entries (grown on
+ * demand), the device argument table and four pinned host copies of it (a
+ * call waits until the replay four calls earlier has read its copy), all
+ * kept until gk_destroy.  Calls that overlap on one context race on that
+ * scratch: one gk_filter_mixed at a time per context, on one stream.
+ * Asynchronous on stream.
  */
 int gk_filter_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream);
 

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -229,6 +230,14 @@ void gk_destroy(gk_ctx *ctx)
             (void)hipFree(ctx->d_resid);
         if (ctx->capture_stream)
             (void)hipStreamDestroy(ctx->capture_stream);
+        if (ctx->d_table)
+            (void)hipFree(ctx->d_table);
+        for (int k = 0; k < gk_ctx::TABLE_RING; ++k) {
+            if (ctx->h_table[k])
+                (void)hipHostFree(ctx->h_table[k]);
+            if (ctx->table_ev[k])
+                (void)hipEventDestroy(ctx->table_ev[k]);
+        }
         gk_detail_free_host_pipe(ctx);
         if (ctx->d_verify_list)
             (void)hipFree(ctx->d_verify_list);
@@ -525,6 +534,23 @@ int ensure_mixed_scratch(gk_ctx *ctx, uint64_t n_pairs)
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_filter_mixed: hipStreamCreate");
     }
+    if (!ctx->d_table) {
+        e = gk_dmalloc(&ctx->d_table, sizeof(gkd::BatchTable));
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_filter_mixed: hipMalloc table");
+    }
+    for (int k = 0; k < gk_ctx::TABLE_RING; ++k) {
+        if (!ctx->h_table[k]) {
+            e = gk_hmalloc(&ctx->h_table[k], sizeof(gkd::BatchTable));
+            if (e != hipSuccess)
+                return hip_fail(ctx, e, "gk_filter_mixed: pinned table");
+        }
+        if (!ctx->table_ev[k]) {
+            e = hipEventCreateWithFlags(&ctx->table_ev[k], hipEventDisableTiming);
+            if (e != hipSuccess)
+                return hip_fail(ctx, e, "gk_filter_mixed: hipEventCreate");
+        }
+    }
     return GK_OK;
 }
 
@@ -637,30 +663,36 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
         return st;
     a.stream_reads = 0;     // the mixed kernel reads each pair entry twice
     const uint32_t wmax = (b->max_read_len + 31) / 32;
-    gkd::MixedArgs x{};   // zeroed: its bytes are part of the graph key
+    gkd::MixedArgs x{};
     if ((st = mixed_args(ctx, ctx->mixed, wmax, b->read_layout, x)) != GK_OK)
         return st;
     hipError_t e;
-    if (!ctx->use_graph) {
-        e = gkd::launch_mixed(a, x, wmax, b->read_layout, (hipStream_t)stream);
+    const hipStream_t hs = (hipStream_t)stream;
+    // Direct launches: graphs off, variant semantics (their own kernels), or
+    // a batch of more than one launch chunk (2^30 pairs).
+    if (!ctx->use_graph || a.flags != 0u || b->n_pairs > (1ull << 30)) {
+        e = gkd::launch_mixed(a, x, wmax, b->read_layout, hs);
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_filter_mixed: launch");
         return GK_OK;
     }
-    // The launch sequence is captured once per distinct (arguments, tuning)
-    // and replayed from the graph afterwards.
-    std::vector<uint8_t> key(sizeof a + sizeof x + 8);
-    std::memcpy(key.data(), &a, sizeof a);
-    std::memcpy(key.data() + sizeof a, &x, sizeof x);
-    const uint32_t tail[2] = {wmax, b->read_layout};
-    std::memcpy(key.data() + sizeof a + sizeof x, tail, 8);
+    // Graph: the captured sequence (reset, persistent kernel, residual pass)
+    // reads the batch from the context's device table, which a copy on the
+    // stream fills before each replay; so one graph serves every batch of a
+    // given shape (words per mask, layout) and tuning, captured the first
+    // time that pair is seen.
+    x.table = ctx->d_table;
+    const uint32_t shape[8] = {wmax <= 4 ? 4u : (wmax <= 10 ? 10u : 16u), b->read_layout, x.tile,
+                               x.ppl, x.sort_e, x.blocks, x.resid_blocks, 0u};
+    std::vector<uint8_t> key(sizeof shape);
+    std::memcpy(key.data(), shape, sizeof shape);
     if (!ctx->graph_exec || key != ctx->graph_key) {
         drop_graph(ctx);
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed);
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_filter_mixed: begin capture");
-        hipError_t le = gkd::launch_mixed(a, x, wmax, b->read_layout, ctx->capture_stream);
+        hipError_t le = gkd::launch_mixed_table(x, wmax, b->read_layout, ctx->capture_stream);
         e = hipStreamEndCapture(ctx->capture_stream, &graph);
         if (le != hipSuccess || e != hipSuccess) {
             if (graph)
@@ -675,9 +707,30 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
         }
         ctx->graph_key = key;
     }
-    e = hipGraphLaunch(ctx->graph_exec, (hipStream_t)stream);
+    // This call's table: a pinned slot no earlier replay still reads.
+    const int slot = (int)(ctx->table_next++ % gk_ctx::TABLE_RING);
+    if (ctx->table_used[slot] && (e = hipEventSynchronize(ctx->table_ev[slot])) != hipSuccess)
+        return hip_fail(ctx, e, "gk_filter_mixed: table slot");
+    gkd::BatchTable *h = ctx->h_table[slot];
+    h->n_batches = 1;
+    h->prefix[0] = 0;
+    h->prefix[1] = (uint32_t)((b->n_pairs + x.tile - 1) / x.tile);
+    h->args[0] = a;
+    h->args[0].accept_bits = nullptr;
+    const size_t bytes = offsetof(gkd::BatchTable, args) + sizeof(gkd::FilterArgs);
+    e = hipMemcpyAsync(ctx->d_table, h, bytes, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = hipGraphLaunch(ctx->graph_exec, hs);
+    if (e == hipSuccess)
+        e = hipEventRecord(ctx->table_ev[slot], hs);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "gk_filter_mixed: graph launch");
+    ctx->table_used[slot] = true;
+    if (a.accept_bits) {
+        e = gkd::launch_accept_bits(a.accept, b->n_pairs, a.accept_bits, hs);
+        if (e != hipSuccess)
+            return hip_fail(ctx, e, "gk_filter_mixed: accept bits");
+    }
     return GK_OK;
 }
 

@@ -68,7 +68,16 @@ struct gk_ctx {
     uint64_t resid_cap = 0;
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    std::vector<uint8_t> graph_key;
+    std::vector<uint8_t> graph_key;           // shape and tuning of graph_exec
+    // the batch argument table the graph reads (device), and a ring of
+    // pinned host copies it is filled from, each reusable once its event
+    // (recorded after the graph launch that read it) has fired
+    static constexpr int TABLE_RING = 4;
+    gkd::BatchTable *d_table = nullptr;
+    gkd::BatchTable *h_table[TABLE_RING] = {};
+    hipEvent_t table_ev[TABLE_RING] = {};
+    bool table_used[TABLE_RING] = {};
+    uint32_t table_next = 0;
     HostPipe host;                            // gk_filter_host
     uint32_t *d_verify_list = nullptr;        // gk_verify: selected pairs (verify_cap
                                               // words), per-workgroup counts, deferred
@@ -142,6 +151,10 @@ hipError_t mixed_blocks_per_cu(uint32_t wmax, uint32_t layout, uint32_t tile, ui
 // table at x.table; the tile count is read from the table on the device, so
 // the sequence can be captured once and replayed with new table contents.
 hipError_t launch_mixed_table(const MixedArgs &x, uint32_t wmax, uint32_t layout, hipStream_t s);
+// Accept bits of n accept codes (bit j of word t: pair 64t + j is ACCEPT or
+// UNDEFINED).
+hipError_t launch_accept_bits(const uint8_t *accept, uint64_t n, unsigned long long *bits,
+                              hipStream_t s);
 size_t mixed_lds_size(uint32_t tile);
 
 // Launch the plain filter with `words` 32-base words per mask (1..16).

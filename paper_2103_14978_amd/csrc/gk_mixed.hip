@@ -485,6 +485,17 @@ hipError_t launch_mixed_table(const MixedArgs &x, uint32_t wmax, uint32_t layout
               : launch_table_wl<16, GK_READS_SPLIT>(x, s);
 }
 
+hipError_t launch_accept_bits(const uint8_t *accept, uint64_t n, unsigned long long *bits,
+                              hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    const uint64_t words = (n + 63) / 64;
+    hipLaunchKernelGGL(k_accept_bits, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, s,
+                       accept, n, bits);
+    return hipGetLastError();
+}
+
 hipError_t launch_mixed(const FilterArgs &a, const MixedArgs &x, uint32_t wmax, uint32_t layout,
                         hipStream_t s)
 {
