@@ -1,6 +1,12 @@
 """Parity at the workloads' full sizes, in the launch configurations the
-benchmark times: outputs sampled against the oracle pair by pair, plus
-properties checked on every pair."""
+benchmark times: every pair against the oracle (directly at config 1, by a
+digest of the oracle's outputs computed offline at configs 2 and 3, by
+request at config 4), samples against the oracle pair by pair (which name the
+first differing pair), and properties checked on every pair."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -19,6 +25,24 @@ def check_properties(a, s, e, m, label):
     assert set(np.unique(a)) <= {0, 1}, label
     assert np.all(s.astype(np.int64) <= m), label
     assert np.array_equal(a == 1, s.astype(np.int64) <= e), label
+
+
+DIGESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                       "fullsize_digests.json")
+
+
+def digest_check(a, s, label):
+    """Every pair: the SHA-256 of the outputs (accept codes, then estimates as
+    little-endian uint16) equals the one tests/golden/make_fullsize_digests.py
+    computed from the oracle on the same seeded workload."""
+    with open(DIGESTS) as f:
+        want = json.load(f)["points"][label]
+    assert len(a) == want["n_pairs"], label
+    h = hashlib.sha256()
+    h.update(np.ascontiguousarray(a, dtype="u1").tobytes())
+    h.update(np.ascontiguousarray(s, dtype="<u2").tobytes())
+    assert int((a == 1).sum()) == want["accepted"], f"{label}: accepted count"
+    assert h.hexdigest() == want["sha256"], f"{label}: outputs differ from the oracle's"
 
 
 def sample_check(ref, ps, a, s, e, k, seed, label):
@@ -81,7 +105,8 @@ def test_config1_full(gkctx, ref100m):
 
 @pytest.mark.parametrize("m,es", [(150, (3, 7, 15)), (250, (5, 12, 25))])
 def test_config2_full(gkctx, ref100m, m, es):
-    """2^25 pairs at each (read length, e), several candidates per read."""
+    """2^25 pairs at each (read length, e), several candidates per read:
+    every pair against the oracle's digest."""
     ref = ref100m
     gk.gk_load_reference(gkctx, ref)
     for e in es:
@@ -95,6 +120,7 @@ def test_config2_full(gkctx, ref100m, m, es):
         a, s = device.results(dp)
         check_properties(a, s, e, m, f"config2 m={m} e={e}")
         sample_check(ref, ps, a, s, e, 1 << 13, e, f"config2 m={m} e={e}")
+        digest_check(a, s, f"config2 m={m} e={e}")
         say(f"case: config2 full verify m={m} e={e}")
         verify_check(gkctx, ref, ps, b, dp, a, e, 1 << 13, 100 + e, f"config2 verify m={m} e={e}")
         del dr, dp, b
@@ -102,7 +128,7 @@ def test_config2_full(gkctx, ref100m, m, es):
 
 def test_config3_full(gkctx, ref100m):
     """2^26 mixed pairs: the autotuned persistent launch from its graph equals
-    the plain launch on every pair and the oracle on a sample."""
+    the plain launch and the oracle's digest on every pair."""
     ref = ref100m
     gk.gk_load_reference(gkctx, ref)
     ps = gen.c3_pairs(ref)
@@ -123,6 +149,7 @@ def test_config3_full(gkctx, ref100m):
     a2, s2 = device.results(dp2)
     assert_same(a, s, a2, s2, "config3 mixed vs plain")
     sample_check(ref, ps, a, s, ps.e, 1 << 15, 3, "config3 sample")
+    digest_check(a, s, "config3")
     for opt, val in ((gk.GK_OPT_MIXED_TILE, 4096), (gk.GK_OPT_MIXED_PAIRS_PER_LANE, 1),
                      (gk.GK_OPT_MIXED_SORT_E, 1), (gk.GK_OPT_MIXED_BLOCKS_PER_CU, 0)):
         gk.gk_set_option(gkctx, opt, val)
