@@ -243,6 +243,8 @@ void gk_destroy(gk_ctx *ctx)
             (void)hipFree(ctx->d_verify_list);
         if (ctx->d_verify_count)
             (void)hipFree(ctx->d_verify_count);
+        if (ctx->d_reads_rm)
+            (void)hipFree(ctx->d_reads_rm);
     }
     delete ctx;
 }
@@ -618,8 +620,9 @@ int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *d
     if (!g.ok)
         return fail(ctx, GK_EDEVICE, "gk_verify: hipSetDevice failed");
     // The pair list (one word per pair of a chunk of up to 2^30), one word
-    // per 4096 of those pairs for the listing's per-workgroup counts, and the
-    // list of pairs the paired verify kernel leaves to the one-pair kernel.
+    // per 4096 of those pairs for the listing's per-workgroup counts, the
+    // list of pairs the paired verify kernel leaves to the one-pair kernel,
+    // and the key counts and cursors of the listing by length and e.
     const uint64_t need = std::min<uint64_t>(b->n_pairs, 1ull << 30);
     if (need > ctx->verify_cap) {
         if (ctx->d_verify_list)
@@ -627,7 +630,8 @@ int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *d
         ctx->d_verify_list = nullptr;
         ctx->verify_cap = 0;
         hipError_t e = gk_dmalloc(&ctx->d_verify_list,
-                                 (2 * need + (need + 4095) / 4096) * sizeof(uint32_t));
+                                 (2 * need + (need + 4095) / 4096 + gkd::VERIFY_BIN_WORDS) *
+                                     sizeof(uint32_t));
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_verify: hipMalloc list");
         ctx->verify_cap = need;
@@ -637,11 +641,31 @@ int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *d
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_verify: hipMalloc count");
     }
+    // With a read index per pair and a threshold per pair, the listing orders
+    // the pairs by (length, e), which scatters each read's candidates: the
+    // one-pair-per-lane kernel then takes the reads from a row-major copy
+    // (one run of loads per read instead of a line per transposed row).
+    uint32_t *rm = nullptr;
+    if (b->pair_read && b->e && b->n_reads > 0) {
+        const uint64_t rm_words = (uint64_t)b->n_reads * gkd::verify_rm_stride(a.rows);
+        if (rm_words > ctx->reads_rm_cap) {
+            if (ctx->d_reads_rm)
+                (void)hipFree(ctx->d_reads_rm);
+            ctx->d_reads_rm = nullptr;
+            ctx->reads_rm_cap = 0;
+            hipError_t e = gk_dmalloc(&ctx->d_reads_rm, rm_words * sizeof(uint32_t));
+            if (e != hipSuccess)
+                return hip_fail(ctx, e, "gk_verify: hipMalloc row-major reads");
+            ctx->reads_rm_cap = rm_words;
+        }
+        rm = ctx->d_reads_rm;
+    }
     const uint32_t words = (b->max_read_len + 31) / 32;
     uint32_t *groups = ctx->d_verify_list + ctx->verify_cap;
     uint32_t *deferred = groups + (ctx->verify_cap + 4095) / 4096;
+    uint32_t *bins = deferred + ctx->verify_cap;
     hipError_t e = gkd::launch_verify(a, accept, dist, ctx->d_verify_list, groups, deferred,
-                                      ctx->d_verify_count, words, b->read_layout,
+                                      ctx->d_verify_count, bins, rm, words, b->read_layout,
                                       ctx->cu_count, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(ctx, e, "gk_verify: launch");

@@ -85,6 +85,8 @@ struct gk_ctx {
     // d_verify_count: [0] selected pairs, [1] deferred pairs
     uint32_t *d_verify_count = nullptr;
     uint64_t verify_cap = 0;
+    uint32_t *d_reads_rm = nullptr;           // gk_verify: row-major copy of the reads
+    uint64_t reads_rm_cap = 0;                // (words)
 };
 
 // Releases the buffers, streams and events of gk_filter_host.

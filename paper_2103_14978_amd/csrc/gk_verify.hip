@@ -234,10 +234,77 @@ __device__ __forceinline__ uint32_t verify_pair(const PairIdx &p, const PairData
                       : band_distance<W, B64>(rh, rl, gh, gl, m, p.e);
 }
 
-// Persistent over the list, one pair per lane.
-template <int W, int L>
+// A pair's loads as load_data does them, but with the read's words taken
+// from a row-major copy of the reads (read r's rows at rm[r * rm_stride ..],
+// rm_stride a multiple of 4 words, zero past the rows): one read is one run
+// of 16-byte loads from one or two lines, instead of a line per row of the
+// transposed layout (whose rows only share lines between neighbouring reads).
+template <int W>
+__device__ __forceinline__ void load_data_rm(const FilterArgs &a, const PairIdx &p,
+                                             PairData<W> &d, const uint32_t *rm,
+                                             uint32_t rm_stride)
+{
+    const uint32_t r = p.r < a.n_reads ? p.r : 0u;
+    const uint32_t pos = p.pos < a.ref_len ? p.pos : 0u;
+    d.m = a.n_reads ? (uint32_t)a.read_len[r] : 0u;
+    const uint4 *q = reinterpret_cast<const uint4 *>(rm + (size_t)r * rm_stride);
+#pragma unroll
+    for (int j = 0; j < 2 * W; j += 4) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (a.n_reads && (uint32_t)j < a.rows)
+            v = q[j / 4];
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (j + k < 2 * W)
+                d.words[j + k] = w4[k];
+    }
+    // the window, as load_data takes it
+    const uint32_t w0 = pos >> 5;
+    const uint32_t span = (pos & 31u) + a.max_read_len;
+    const uint32_t nw = (span + 31u) >> 5;
+    const bool use_b = a.ref_planes_b != nullptr && w0 >= REF_SHIFT_WORDS &&
+                       (w0 & (LINE_WORDS - 1u)) + nw > LINE_WORDS;
+    const uint2 *src = use_b ? a.ref_planes_b + (w0 - REF_SHIFT_WORDS) : a.ref_planes + w0;
+#pragma unroll
+    for (int w = 0; w <= W; ++w)
+        d.win[w] = 32u * w < span ? src[w] : make_uint2(0u, 0u);
+}
+
+// Transposed read rows (word j of read r at reads[j * pitch + r]) to the
+// row-major copy load_data_rm takes: a workgroup stages 256 reads' rows in
+// LDS (each row read with consecutive lanes on consecutive words) and each
+// lane writes its read's rm_stride words as 16-byte stores (consecutive lanes,
+// consecutive reads).
+__global__ __launch_bounds__(256) void k_reads_rowmajor(const uint32_t *reads, uint32_t pitch,
+                                                        uint32_t rows, uint32_t n_reads,
+                                                        uint32_t rm_stride, uint32_t *rm)
+{
+    extern __shared__ uint32_t rm_lds[];
+    const uint32_t t = threadIdx.x;
+    const uint32_t r0 = blockIdx.x * 256u;
+    const uint32_t r = r0 + t;
+    const uint32_t ld = rm_stride + 1u;      // odd pitch: a row's words hit distinct banks
+    for (uint32_t j = 0; j < rows; ++j)
+        rm_lds[t * ld + j] = r < n_reads ? reads[(size_t)j * pitch + r] : 0u;
+    for (uint32_t j = rows; j < rm_stride; ++j)
+        rm_lds[t * ld + j] = 0u;
+    __syncthreads();
+    if (r < n_reads) {
+        uint4 *out = reinterpret_cast<uint4 *>(rm + (size_t)r * rm_stride);
+        for (uint32_t j = 0; j < rm_stride; j += 4)
+            out[j / 4] = make_uint4(rm_lds[t * ld + j], rm_lds[t * ld + j + 1],
+                                    rm_lds[t * ld + j + 2], rm_lds[t * ld + j + 3]);
+    }
+}
+
+// Persistent over the list, one pair per lane; RM: the reads come from the
+// row-major copy rm (load_data_rm).
+template <int W, int L, bool RM = false>
 __global__ __launch_bounds__(256) void k_verify(FilterArgs a, const uint32_t *list,
-                                                const uint32_t *count, uint16_t *dist)
+                                                const uint32_t *count, uint16_t *dist,
+                                                const uint32_t *rm = nullptr,
+                                                uint32_t rm_stride = 0)
 {
     const uint32_t n = *count;
     const uint32_t stride = gridDim.x * 256u;
@@ -245,7 +312,10 @@ __global__ __launch_bounds__(256) void k_verify(FilterArgs a, const uint32_t *li
         const uint32_t i = list[t];
         const PairIdx p = load_idx(a, i);
         PairData<W> d;
-        load_data<W>(a, p, d);
+        if constexpr (RM)
+            load_data_rm<W>(a, p, d, rm, rm_stride);
+        else
+            load_data<W>(a, p, d);
         uint32_t m, out = GK_EST_NONE;
         if (p.e <= GK_VERIFY_MAX_E && pair_gate<W>(a, p, d, m) == PAIR_OK)
             out = verify_pair<W, L>(p, d, m);
@@ -578,9 +648,123 @@ __global__ __launch_bounds__(256) void k_select_write(FilterArgs a, const uint8_
     }
 }
 
+// ---- listing by (read length in words, e) over the whole batch ----------
+//
+// With a threshold per pair, a wave of the one-pair-per-lane kernel takes its
+// scalar path (one band width, one shift schedule, scalar trip counts) only
+// if its pairs share e and the read length.  After the filter a 4096-pair
+// group lists a few hundred pairs over as many (length, e) combinations, so
+// sorting within groups leaves nearly every wave mixed.  These kernels sort
+// the listed pairs of the whole batch by key = (ceil(m / 32) - 1) * 32 +
+// min(e, 31) (512 keys; within a key the lengths differ in the last word
+// only): counts per key with one atomic per (group, key), key starts by a
+// scan, then each group reserves its run in each key with one more atomic
+// and writes its pairs there (the order within a key does not matter).
+constexpr uint32_t NKEYS = 512u;
+
+__device__ __forceinline__ void bin_keys(const FilterArgs &a, uint32_t i0, uint32_t sel,
+                                         uint32_t (&key)[SEL_PER_LANE])
+{
+    FilterArgs la = a;
+    la.e_pair = nullptr;                 // plain read lengths
+    uint32_t len[SEL_PER_LANE];
+    length_keys(la, i0, sel, len);
+#pragma unroll
+    for (uint32_t j = 0; j < SEL_PER_LANE; ++j) {
+        const uint32_t e = (sel & (1u << j)) ? (uint32_t)a.e_pair[i0 + j] : 0u;
+        key[j] = len[j] ? ((len[j] + 31u) / 32u - 1u) * 32u + (e < 31u ? e : 31u) : 0u;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_zero(uint32_t *bins)
+{
+    for (uint32_t b = threadIdx.x; b < 2u * NKEYS; b += 256u)
+        bins[b] = 0u;
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_bin_count(FilterArgs a, const uint8_t *accept,
+                                                   uint32_t n, uint32_t *bins, uint16_t *dist)
+{
+    __shared__ uint32_t h[NKEYS];
+    for (uint32_t b = threadIdx.x; b < NKEYS; b += 256u)
+        h[b] = 0u;
+    __syncthreads();
+    const uint32_t i0 = blockIdx.x * SEL_PER_GROUP + threadIdx.x * SEL_PER_LANE;
+    const uint32_t sel = select_bits<VEC>(accept, n, i0, dist, true);
+    uint32_t key[SEL_PER_LANE];
+    bin_keys(a, i0, sel, key);
+#pragma unroll
+    for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+        if (sel & (1u << j))
+            atomicAdd(&h[key[j]], 1u);
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < NKEYS; b += 256u)
+        if (h[b])
+            atomicAdd(&bins[b], h[b]);
+}
+
+// bins[0, NKEYS): counts -> starts; bins[NKEYS, 2 NKEYS): cursors (zero);
+// count[0] = the total, count[1] = 0.
+__global__ __launch_bounds__(64) void k_bin_scan(uint32_t *bins, uint32_t *count)
+{
+    const uint32_t lane = threadIdx.x;
+    constexpr uint32_t PER = NKEYS / 64u;
+    uint32_t local[PER], sum = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        local[q] = bins[lane * PER + q];
+        sum += local[q];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t t = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o)
+            incl += t;
+    }
+    uint32_t run = incl - sum;
+#pragma unroll
+    for (uint32_t q = 0; q < PER; ++q) {
+        bins[lane * PER + q] = run;
+        run += local[q];
+    }
+    if (lane == 63u) {
+        count[0] = incl;
+        count[1] = 0u;
+    }
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_bin_write(FilterArgs a, const uint8_t *accept,
+                                                   uint32_t n, uint32_t *bins, uint32_t *list)
+{
+    __shared__ uint32_t h[NKEYS];
+    for (uint32_t b = threadIdx.x; b < NKEYS; b += 256u)
+        h[b] = 0u;
+    __syncthreads();
+    const uint32_t i0 = blockIdx.x * SEL_PER_GROUP + threadIdx.x * SEL_PER_LANE;
+    const uint32_t sel = select_bits<VEC>(accept, n, i0, nullptr, false);
+    uint32_t key[SEL_PER_LANE], rank[SEL_PER_LANE];
+    bin_keys(a, i0, sel, key);
+#pragma unroll
+    for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+        rank[j] = (sel & (1u << j)) ? atomicAdd(&h[key[j]], 1u) : 0u;
+    __syncthreads();
+    // this group's run in each key: key start + a reservation on its cursor
+    for (uint32_t b = threadIdx.x; b < NKEYS; b += 256u)
+        if (h[b])
+            h[b] = bins[b] + atomicAdd(&bins[NKEYS + b], h[b]);
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
+        if (sel & (1u << j))
+            list[h[key[j]] + rank[j]] = i0 + j;
+}
+
 // Resident 256-lane workgroups per CU of k_verify (PAIRED false) or
 // k_verify_paired (true).
-template <int W, int L, bool PAIRED>
+template <int W, int L, bool PAIRED, bool RM = false>
 hipError_t verify_blocks_per_cu(int &out)
 {
     static int per_cu = -1;
@@ -589,7 +773,7 @@ hipError_t verify_blocks_per_cu(int &out)
         hipError_t e = PAIRED ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
                                     &v, k_verify_paired<W, L>, 256, 0)
                               : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                                    &v, k_verify<W, L>, 256, 0);
+                                    &v, k_verify<W, L, RM>, 256, 0);
         if (e != hipSuccess)
             return e;
         per_cu = v > 0 ? v : 1;
@@ -600,16 +784,27 @@ hipError_t verify_blocks_per_cu(int &out)
 
 template <int W, int L>
 hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, uint32_t *list,
-                     uint32_t *groups_buf, uint32_t *deferred, uint32_t *count, int cus,
-                     hipStream_t s)
+                     uint32_t *groups_buf, uint32_t *deferred, uint32_t *count, uint32_t *bins,
+                     uint32_t *rm, int cus, hipStream_t s)
 {
     const bool paired = W <= 8 && a.e_pair == nullptr && a.e_uniform <= 7u;
+    const bool use_rm = rm != nullptr && !paired;
+    const uint32_t rm_stride = (a.rows + 3u) & ~3u;
     int per_cu = 1, per_cu1 = 1;
-    hipError_t oe = verify_blocks_per_cu<W, L, false>(per_cu1);
+    hipError_t oe = use_rm ? verify_blocks_per_cu<W, L, false, true>(per_cu1)
+                           : verify_blocks_per_cu<W, L, false>(per_cu1);
     if (oe == hipSuccess && paired)
         oe = verify_blocks_per_cu<W, L, true>(per_cu);
     if (oe != hipSuccess)
         return oe;
+    if (use_rm && a.n_reads > 0) {
+        hipLaunchKernelGGL(k_reads_rowmajor, dim3((a.n_reads + 255u) / 256u), dim3(256),
+                           (size_t)256u * (rm_stride + 1u) * 4u, s, a.reads, a.pitch, a.rows,
+                           a.n_reads, rm_stride, rm);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
     const uint64_t CHUNK = 1ull << 30;
     for (uint64_t first = 0; first < a.n_pairs; first += CHUNK) {
         FilterArgs c = a;
@@ -628,19 +823,38 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
         const uint64_t want = (n + 255) / 256;
         const uint32_t groups = (uint32_t)((n + SEL_PER_GROUP - 1) / SEL_PER_GROUP);
         const bool vec = ((uintptr_t)acc & 15u) == 0 && ((uintptr_t)out & 15u) == 0;
-        if (vec)
-            hipLaunchKernelGGL(k_select_count<true>, dim3(groups), dim3(256), 0, s, acc,
-                               (uint32_t)n, groups_buf, out);
-        else
-            hipLaunchKernelGGL(k_select_count<false>, dim3(groups), dim3(256), 0, s, acc,
-                               (uint32_t)n, groups_buf, out);
-        hipLaunchKernelGGL(k_select_scan, dim3(1), dim3(1024), 0, s, groups_buf, groups, count);
-        if (vec)
-            hipLaunchKernelGGL(k_select_write<true>, dim3(groups), dim3(256), 0, s, c, acc,
-                               (uint32_t)n, groups_buf, list);
-        else
-            hipLaunchKernelGGL(k_select_write<false>, dim3(groups), dim3(256), 0, s, c, acc,
-                               (uint32_t)n, groups_buf, list);
+        if (c.e_pair) {
+            // per-pair e: listed by (length in words, e) over the whole batch
+            hipLaunchKernelGGL(k_bin_zero, dim3(1), dim3(256), 0, s, bins);
+            if (vec)
+                hipLaunchKernelGGL(k_bin_count<true>, dim3(groups), dim3(256), 0, s, c, acc,
+                                   (uint32_t)n, bins, out);
+            else
+                hipLaunchKernelGGL(k_bin_count<false>, dim3(groups), dim3(256), 0, s, c, acc,
+                                   (uint32_t)n, bins, out);
+            hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(64), 0, s, bins, count);
+            if (vec)
+                hipLaunchKernelGGL(k_bin_write<true>, dim3(groups), dim3(256), 0, s, c, acc,
+                                   (uint32_t)n, bins, list);
+            else
+                hipLaunchKernelGGL(k_bin_write<false>, dim3(groups), dim3(256), 0, s, c, acc,
+                                   (uint32_t)n, bins, list);
+        } else {
+            if (vec)
+                hipLaunchKernelGGL(k_select_count<true>, dim3(groups), dim3(256), 0, s, acc,
+                                   (uint32_t)n, groups_buf, out);
+            else
+                hipLaunchKernelGGL(k_select_count<false>, dim3(groups), dim3(256), 0, s, acc,
+                                   (uint32_t)n, groups_buf, out);
+            hipLaunchKernelGGL(k_select_scan, dim3(1), dim3(1024), 0, s, groups_buf, groups,
+                               count);
+            if (vec)
+                hipLaunchKernelGGL(k_select_write<true>, dim3(groups), dim3(256), 0, s, c, acc,
+                                   (uint32_t)n, groups_buf, list);
+            else
+                hipLaunchKernelGGL(k_select_write<false>, dim3(groups), dim3(256), 0, s, c, acc,
+                                   (uint32_t)n, groups_buf, list);
+        }
         // Grids of up to 8 times the resident workgroups: later workgroups
         // start as earlier ones finish, so the waves' gathers do not all come
         // at once (measured faster than one resident round at every sweep
@@ -655,10 +869,14 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
             // one resident round)
             const uint64_t vbd = want < (uint64_t)cus * per_cu1 ? want : (uint64_t)cus * per_cu1;
             hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vbd), dim3(256), 0, s, c,
-                               (const uint32_t *)deferred, (const uint32_t *)(count + 1), out);
+                               (const uint32_t *)deferred, (const uint32_t *)(count + 1), out,
+                               (const uint32_t *)nullptr, 0u);
+        } else if (use_rm) {
+            hipLaunchKernelGGL((k_verify<W, L, true>), dim3((uint32_t)vb1), dim3(256), 0, s, c,
+                               list, count, out, (const uint32_t *)rm, rm_stride);
         } else {
             hipLaunchKernelGGL((k_verify<W, L>), dim3((uint32_t)vb1), dim3(256), 0, s, c, list,
-                               count, out);
+                               count, out, (const uint32_t *)nullptr, 0u);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
@@ -669,26 +887,42 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
 
 template <int L>
 hipError_t verify_l(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, uint32_t *list,
-                    uint32_t *groups_buf, uint32_t *deferred, uint32_t *count, uint32_t words,
-                    int cus, hipStream_t s)
+                    uint32_t *groups_buf, uint32_t *deferred, uint32_t *count, uint32_t *bins,
+                    uint32_t *rm, uint32_t words, int cus, hipStream_t s)
 {
     switch (words) {
-    case 1: return verify_wl<1, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 2: return verify_wl<2, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 3: return verify_wl<3, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 4: return verify_wl<4, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 5: return verify_wl<5, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 6: return verify_wl<6, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 7: return verify_wl<7, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 8: return verify_wl<8, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 9: return verify_wl<9, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 10: return verify_wl<10, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 11: return verify_wl<11, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 12: return verify_wl<12, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 13: return verify_wl<13, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 14: return verify_wl<14, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 15: return verify_wl<15, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
-    case 16: return verify_wl<16, L>(a, accept, dist, list, groups_buf, deferred, count, cus, s);
+    case 1: return verify_wl<1, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 2: return verify_wl<2, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 3: return verify_wl<3, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 4: return verify_wl<4, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 5: return verify_wl<5, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 6: return verify_wl<6, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 7: return verify_wl<7, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 8: return verify_wl<8, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 9: return verify_wl<9, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 10: return verify_wl<10, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 11: return verify_wl<11, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 12: return verify_wl<12, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 13: return verify_wl<13, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 14: return verify_wl<14, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 15: return verify_wl<15, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
+    case 16: return verify_wl<16, L>(a, accept, dist, list, groups_buf, deferred, count, bins, rm, cus,
+                                  s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -697,13 +931,14 @@ hipError_t verify_l(const FilterArgs &a, const uint8_t *accept, uint16_t *dist, 
 
 hipError_t launch_verify(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
                          uint32_t *list, uint32_t *groups, uint32_t *deferred, uint32_t *count,
-                         uint32_t words, uint32_t layout, int cus, hipStream_t s)
+                         uint32_t *bins, uint32_t *reads_rm, uint32_t words, uint32_t layout,
+                         int cus, hipStream_t s)
 {
     return layout == GK_READS_INTERLEAVED
                ? verify_l<GK_READS_INTERLEAVED>(a, accept, dist, list, groups, deferred, count,
-                                                words, cus, s)
-               : verify_l<GK_READS_SPLIT>(a, accept, dist, list, groups, deferred, count, words,
-                                          cus, s);
+                                                bins, reads_rm, words, cus, s)
+               : verify_l<GK_READS_SPLIT>(a, accept, dist, list, groups, deferred, count, bins,
+                                          reads_rm, words, cus, s);
 }
 
 }  // namespace gkd
