@@ -19,7 +19,7 @@ hipError_t launch_verify(const FilterArgs &a, const uint8_t *accept, uint16_t *d
                          uint32_t *bins, uint32_t *reads_rm, uint32_t words, uint32_t layout,
                          int cus, hipStream_t s);
 
-constexpr uint32_t VERIFY_BIN_WORDS = 1024u;
+constexpr uint32_t VERIFY_BIN_WORDS = 3u * 512u * 32u;
 
 // Words per read of the row-major copy: rows rounded up to a multiple of 4.
 inline uint32_t verify_rm_stride(uint32_t rows) { return (rows + 3u) & ~3u; }

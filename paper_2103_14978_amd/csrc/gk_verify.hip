@@ -657,10 +657,16 @@ __global__ __launch_bounds__(256) void k_select_write(FilterArgs a, const uint8_
 // sorting within groups leaves nearly every wave mixed.  These kernels sort
 // the listed pairs of the whole batch by key = (ceil(m / 32) - 1) * 32 +
 // min(e, 31) (512 keys; within a key the lengths differ in the last word
-// only): counts per key with one atomic per (group, key), key starts by a
-// scan, then each group reserves its run in each key with one more atomic
-// and writes its pairs there (the order within a key does not matter).
+// only): each group counts its pairs per key in LDS and adds the counts to
+// one of BIN_COPIES copies of the key counts (by group number, so that no
+// count is added to by more than 1 / BIN_COPIES of the groups); a scan turns
+// the counts into starts, key-major and copy-minor; each group then reserves
+// its run in its copy of each key with one atomic and writes its pairs there
+// (the order within a key does not matter: every result is written at its
+// own pair index).
 constexpr uint32_t NKEYS = 512u;
+constexpr uint32_t BIN_COPIES = 32u;
+constexpr uint32_t BIN_CELLS = NKEYS * BIN_COPIES;   // counts, then cursors, then starts
 
 __device__ __forceinline__ void bin_keys(const FilterArgs &a, uint32_t i0, uint32_t sel,
                                          uint32_t (&key)[SEL_PER_LANE])
@@ -676,9 +682,10 @@ __device__ __forceinline__ void bin_keys(const FilterArgs &a, uint32_t i0, uint3
     }
 }
 
+// counts and cursors to zero
 __global__ __launch_bounds__(256) void k_bin_zero(uint32_t *bins)
 {
-    for (uint32_t b = threadIdx.x; b < 2u * NKEYS; b += 256u)
+    for (uint32_t b = blockIdx.x * 256u + threadIdx.x; b < 2u * BIN_CELLS; b += gridDim.x * 256u)
         bins[b] = 0u;
 }
 
@@ -699,21 +706,24 @@ __global__ __launch_bounds__(256) void k_bin_count(FilterArgs a, const uint8_t *
         if (sel & (1u << j))
             atomicAdd(&h[key[j]], 1u);
     __syncthreads();
+    uint32_t *copy = bins + (blockIdx.x % BIN_COPIES) * NKEYS;
     for (uint32_t b = threadIdx.x; b < NKEYS; b += 256u)
         if (h[b])
-            atomicAdd(&bins[b], h[b]);
+            atomicAdd(&copy[b], h[b]);
 }
 
-// bins[0, NKEYS): counts -> starts; bins[NKEYS, 2 NKEYS): cursors (zero);
-// count[0] = the total, count[1] = 0.
-__global__ __launch_bounds__(64) void k_bin_scan(uint32_t *bins, uint32_t *count)
+// Starts of every (key, copy) cell, key-major: bins[2 BIN_CELLS + c * NKEYS +
+// b] for copy c of key b; count[0] = the total, count[1] = 0.
+__global__ __launch_bounds__(1024) void k_bin_scan(uint32_t *bins, uint32_t *count)
 {
-    const uint32_t lane = threadIdx.x;
-    constexpr uint32_t PER = NKEYS / 64u;
+    __shared__ uint32_t wave_sum[16];
+    constexpr uint32_t PER = BIN_CELLS / 1024u;       // cells per thread, key-major
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
     uint32_t local[PER], sum = 0;
 #pragma unroll
     for (uint32_t q = 0; q < PER; ++q) {
-        local[q] = bins[lane * PER + q];
+        const uint32_t cell = threadIdx.x * PER + q;  // = key * BIN_COPIES + copy
+        local[q] = bins[(cell % BIN_COPIES) * NKEYS + cell / BIN_COPIES];
         sum += local[q];
     }
     uint32_t incl = sum;
@@ -723,14 +733,21 @@ __global__ __launch_bounds__(64) void k_bin_scan(uint32_t *bins, uint32_t *count
         if (lane >= (uint32_t)o)
             incl += t;
     }
-    uint32_t run = incl - sum;
+    if (lane == 63u)
+        wave_sum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w)
+        before += wave_sum[w];
+    uint32_t run = before + incl - sum;
 #pragma unroll
     for (uint32_t q = 0; q < PER; ++q) {
-        bins[lane * PER + q] = run;
+        const uint32_t cell = threadIdx.x * PER + q;
+        bins[2u * BIN_CELLS + (cell % BIN_COPIES) * NKEYS + cell / BIN_COPIES] = run;
         run += local[q];
     }
-    if (lane == 63u) {
-        count[0] = incl;
+    if (threadIdx.x == 1023u) {
+        count[0] = before + incl;
         count[1] = 0u;
     }
 }
@@ -751,10 +768,12 @@ __global__ __launch_bounds__(256) void k_bin_write(FilterArgs a, const uint8_t *
     for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
         rank[j] = (sel & (1u << j)) ? atomicAdd(&h[key[j]], 1u) : 0u;
     __syncthreads();
-    // this group's run in each key: key start + a reservation on its cursor
+    // this group's run in its copy of each key: the cell's start plus a
+    // reservation on the cell's cursor
+    const uint32_t c = (blockIdx.x % BIN_COPIES) * NKEYS;
     for (uint32_t b = threadIdx.x; b < NKEYS; b += 256u)
         if (h[b])
-            h[b] = bins[b] + atomicAdd(&bins[NKEYS + b], h[b]);
+            h[b] = bins[2u * BIN_CELLS + c + b] + atomicAdd(&bins[BIN_CELLS + c + b], h[b]);
     __syncthreads();
 #pragma unroll
     for (uint32_t j = 0; j < SEL_PER_LANE; ++j)
@@ -825,14 +844,14 @@ hipError_t verify_wl(const FilterArgs &a, const uint8_t *accept, uint16_t *dist,
         const bool vec = ((uintptr_t)acc & 15u) == 0 && ((uintptr_t)out & 15u) == 0;
         if (c.e_pair) {
             // per-pair e: listed by (length in words, e) over the whole batch
-            hipLaunchKernelGGL(k_bin_zero, dim3(1), dim3(256), 0, s, bins);
+            hipLaunchKernelGGL(k_bin_zero, dim3(32), dim3(256), 0, s, bins);
             if (vec)
                 hipLaunchKernelGGL(k_bin_count<true>, dim3(groups), dim3(256), 0, s, c, acc,
                                    (uint32_t)n, bins, out);
             else
                 hipLaunchKernelGGL(k_bin_count<false>, dim3(groups), dim3(256), 0, s, c, acc,
                                    (uint32_t)n, bins, out);
-            hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(64), 0, s, bins, count);
+            hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, bins, count);
             if (vec)
                 hipLaunchKernelGGL(k_bin_write<true>, dim3(groups), dim3(256), 0, s, c, acc,
                                    (uint32_t)n, bins, list);
