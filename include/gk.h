@@ -219,7 +219,12 @@ int gk_filter(gk_ctx *ctx, const gk_batch *batch, void *stream);
  * i, and then n_pairs == n_reads) with ref[cand_pos[i], cand_pos[i] + m)
  * under e[i] (or e_uniform when e is NULL); accept[i] and est[i] are as in
  * gk_filter.  The device buffers are the context's, kept for later calls and
- * freed with it.
+ * freed with it.  The chunks (GK_OPT_HOST_CHUNK_PAIRS pairs each) cycle
+ * through three device slots, so device memory is bounded by the chunk size:
+ * about 3 * chunk * (19 + 4 * ceil(max_read_len / 16) + mean read length)
+ * bytes with pair_read NULL.  With pair_read, any pair may use any read, so
+ * every read stays on the device (its text or rows plus its 2-bit words),
+ * and the pairs take 3 * chunk * 12 bytes.
  * Synchronous: returns once every result is in host memory.  Errors:
  * GK_EINVAL for NULL buffers, read_off[0] != 0, decreasing offsets (found
  * while the batch is in flight: the outputs are then unspecified),
@@ -322,6 +327,11 @@ int gk_verify(gk_ctx *ctx, const gk_batch *batch, const uint8_t *accept, uint16_
 #define GK_OPT_SERVER_TICK_PAIRS    9  /* gk_server_start, batched mode:
                                             pairs per tick at most
                                             (4096..2^26, default 2^20)      */
+#define GK_OPT_HOST_CHUNK_PAIRS    10  /* gk_filter_host: pairs per chunk,
+                                            0 (default) = n_pairs / 16
+                                            within 2^20..2^22, else 64..2^26
+                                            (rounded up to a multiple of
+                                            64); sets its device memory     */
 
 /* Set / get a tuning option.  GK_EINVAL for an unknown option or a value out
    of range. */

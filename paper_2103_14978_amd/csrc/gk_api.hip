@@ -841,6 +841,11 @@ int gk_set_option(gk_ctx *ctx, int option, int64_t value)
             return fail(ctx, GK_EINVAL, "gk_set_option: server tick pairs must be 4096..2^26");
         ctx->server_tick_pairs = (uint64_t)value;
         return GK_OK;
+    case GK_OPT_HOST_CHUNK_PAIRS:
+        if (value != 0 && (value < 64 || value > (1ll << 26)))
+            return fail(ctx, GK_EINVAL, "gk_set_option: host chunk pairs must be 0 or 64..2^26");
+        ctx->host_chunk_pairs = (uint64_t)value;
+        return GK_OK;
     default:
         return fail(ctx, GK_EINVAL, "gk_set_option: unknown option");
     }
@@ -877,6 +882,9 @@ int gk_get_option(const gk_ctx *ctx, int option, int64_t *value)
         return GK_OK;
     case GK_OPT_SERVER_TICK_PAIRS:
         *value = (int64_t)ctx->server_tick_pairs;
+        return GK_OK;
+    case GK_OPT_HOST_CHUNK_PAIRS:
+        *value = (int64_t)ctx->host_chunk_pairs;
         return GK_OK;
     default:
         return GK_EINVAL;

@@ -79,9 +79,10 @@ __device__ __forceinline__ uint32_t encode_direct(const uint8_t *ascii, uint64_t
 }
 
 // Fallback encoder: one lane per read, straight from global memory.  Used
-// when the ASCII buffer is not 16-byte aligned.
+// when the ASCII buffer is not 16-byte aligned.  Text offset t is at
+// ascii[t - text_base] (text_base <= every read_off entry).
 template <uint32_t LAYOUT>
-__global__ __launch_bounds__(256) void k_encode_reads(const uint8_t *ascii,
+__global__ __launch_bounds__(256) void k_encode_reads(const uint8_t *ascii, uint64_t text_base,
                                                       const uint64_t *read_off, uint32_t n_reads,
                                                       uint32_t pitch, uint32_t rows,
                                                       uint32_t *packed, uint16_t *len_out,
@@ -90,8 +91,8 @@ __global__ __launch_bounds__(256) void k_encode_reads(const uint8_t *ascii,
     const uint32_t r = blockIdx.x * 256u + threadIdx.x;
     if (r >= n_reads)
         return;
-    const uint64_t off = read_off[r];
-    const uint64_t len = read_off[r + 1] - off;
+    const uint64_t off = read_off[r] - text_base;
+    const uint64_t len = read_off[r + 1] - read_off[r];
     const uint32_t unknown = encode_direct<LAYOUT>(ascii, off, len, r, pitch, rows, packed);
     len_out[r] = (uint16_t)(len < 0xFFFFu ? len : 0xFFFFu);
     if (has_n_out)
@@ -222,6 +223,7 @@ __device__ __forceinline__ uint32_t pack_half(uint32_t lo16, uint32_t hi16)
 
 template <uint32_t LAYOUT>
 __global__ __launch_bounds__(256) void k_encode_reads_staged(const uint8_t *ascii,
+                                                             uint64_t text_base,
                                                              const uint64_t *read_off,
                                                              uint32_t n_reads, uint32_t pitch,
                                                              uint32_t rows, uint32_t *packed,
@@ -236,8 +238,8 @@ __global__ __launch_bounds__(256) void k_encode_reads_staged(const uint8_t *asci
 
     const uint32_t r0 = blockIdx.x * ENC_G;
     const uint32_t r1 = n_reads - r0 < ENC_G ? n_reads : r0 + ENC_G;
-    const uint64_t base = read_off[r0];
-    const uint64_t end = read_off[r1];
+    const uint64_t base = read_off[r0] - text_base;
+    const uint64_t end = read_off[r1] - text_base;
     const uint64_t a0 = base & ~31ull;                  // span start, 32-byte aligned
     // Staged when the span is in order and fits (reads longer than 16 * rows
     // bases, or offsets out of order, take the direct path).
@@ -267,8 +269,8 @@ __global__ __launch_bounds__(256) void k_encode_reads_staged(const uint8_t *asci
     const uint32_t r = r0 + threadIdx.x;
     if (r >= r1)
         return;
-    const uint64_t off = read_off[r];
-    const uint64_t len = read_off[r + 1] - off;
+    const uint64_t off = read_off[r] - text_base;
+    const uint64_t len = read_off[r + 1] - read_off[r];
     const uint64_t use = len < 16ull * rows ? len : 16ull * rows;     // bases encoded
     uint32_t unknown;
     if (staged && off >= base && off + use <= end && use <= len) {
@@ -391,30 +393,32 @@ hipError_t launch_transpose_reads(const uint32_t *rowmajor, uint32_t n_reads, ui
 
 hipError_t launch_encode_reads(const uint8_t *ascii, const uint64_t *read_off, uint32_t n_reads,
                                uint32_t pitch, uint32_t rows, uint32_t layout, uint32_t *packed,
-                               uint16_t *len_out, uint8_t *has_n_out, hipStream_t s)
+                               uint16_t *len_out, uint8_t *has_n_out, hipStream_t s,
+                               uint64_t text_base)
 {
     if (n_reads == 0)
         return hipSuccess;
     const bool split = layout == GK_READS_SPLIT;
-    if (((uintptr_t)ascii & 15u) == 0u) {
+    if ((((uintptr_t)ascii | text_base) & 15u) == 0u) {
         const dim3 grid((n_reads + ENC_G - 1) / ENC_G);
         const size_t lds = enc_lds_bytes(rows);
         if (split)
             hipLaunchKernelGGL(k_encode_reads_staged<GK_READS_SPLIT>, grid, dim3(256), lds, s,
-                               ascii, read_off, n_reads, pitch, rows, packed, len_out, has_n_out);
+                               ascii, text_base, read_off, n_reads, pitch, rows, packed, len_out,
+                               has_n_out);
         else
             hipLaunchKernelGGL(k_encode_reads_staged<GK_READS_INTERLEAVED>, grid, dim3(256), lds,
-                               s, ascii, read_off, n_reads, pitch, rows, packed, len_out,
-                               has_n_out);
+                               s, ascii, text_base, read_off, n_reads, pitch, rows, packed,
+                               len_out, has_n_out);
         return hipGetLastError();
     }
     const dim3 grid((n_reads + 255) / 256);
     if (split)
-        hipLaunchKernelGGL(k_encode_reads<GK_READS_SPLIT>, grid, dim3(256), 0, s, ascii, read_off,
-                           n_reads, pitch, rows, packed, len_out, has_n_out);
+        hipLaunchKernelGGL(k_encode_reads<GK_READS_SPLIT>, grid, dim3(256), 0, s, ascii, text_base,
+                           read_off, n_reads, pitch, rows, packed, len_out, has_n_out);
     else
         hipLaunchKernelGGL(k_encode_reads<GK_READS_INTERLEAVED>, grid, dim3(256), 0, s, ascii,
-                           read_off, n_reads, pitch, rows, packed, len_out, has_n_out);
+                           text_base, read_off, n_reads, pitch, rows, packed, len_out, has_n_out);
     return hipGetLastError();
 }
 

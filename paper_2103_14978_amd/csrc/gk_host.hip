@@ -3,8 +3,10 @@
 // (Sec. 4.3).  The batch is cut into chunks; for each chunk the copies in,
 // the read encoding (Sec. 3.3), the filter and the copies out run on three
 // streams, so chunk j's copies overlap chunk j-1's kernels and chunk j-2's
-// copies out.  The paper instead preprocesses a whole batch, then filters it,
-// then copies it back (Sec. 3.5).
+// copies out.  The chunks cycle through a ring of three device slots, so the
+// device memory is set by the chunk size, not by the batch.  The paper
+// instead preprocesses a whole batch, then filters it, then copies it back
+// (Sec. 3.5).
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -23,79 +25,83 @@ int hip_fail(gk_ctx *ctx, hipError_t e, const char *what)
 }
 
 template <typename T>
-void release(T *&p)
+void release(DevBuf<T> &b)
 {
-    if (p)
-        (void)hipFree(p);
-    p = nullptr;
+    if (b.p)
+        (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
 }
 
+// Grows b to at least n elements (never shrinks it).
 template <typename T>
-hipError_t realloc_device(T *&p, uint64_t count)
+hipError_t fit(DevBuf<T> &b, uint64_t n)
 {
-    release(p);
-    return gk_dmalloc(&p, std::max<uint64_t>(count, 1) * sizeof(T));
+    n = std::max<uint64_t>(n, 1);
+    if (b.p && b.cap >= n)
+        return hipSuccess;
+    release(b);
+    const hipError_t e = gk_dmalloc(&b.p, n * sizeof(T));
+    if (e == hipSuccess)
+        b.cap = n;
+    return e;
 }
 
-// Grows the buffers to the batch (never shrinks them).
-hipError_t ensure_buffers(HostPipe &h, uint64_t ascii_bytes, uint64_t n_reads,
-                          uint64_t packed_words, uint64_t n_pairs, uint32_t chunks)
+void release(HostReads &r)
+{
+    release(r.text);
+    release(r.off);
+    release(r.len);
+    release(r.has_n);
+    release(r.packed);
+}
+
+// Room for n_reads reads of text_bytes bytes of text (or row-major words)
+// and packed_words transposed words.
+hipError_t fit(HostReads &r, uint64_t text_bytes, uint64_t n_reads, uint64_t packed_words)
+{
+    hipError_t e = fit(r.text, text_bytes);
+    if (e == hipSuccess)
+        e = fit(r.off, n_reads + 1);
+    if (e == hipSuccess)
+        e = fit(r.len, n_reads);
+    if (e == hipSuccess)
+        e = fit(r.has_n, n_reads);
+    if (e == hipSuccess)
+        e = fit(r.packed, packed_words);
+    return e;
+}
+
+hipError_t make_event(hipEvent_t &ev)
+{
+    return ev ? hipSuccess : hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+}
+
+hipError_t ensure_streams(HostPipe &h)
 {
     hipError_t e = hipSuccess;
-    if (!h.s_in) {
-        e = hipStreamCreateWithFlags(&h.s_in, hipStreamNonBlocking);
+    for (hipStream_t *s : {&h.s_in, &h.s_comp, &h.s_out})
+        if (e == hipSuccess && !*s)
+            e = hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+    for (HostSlot &sl : h.slot)
+        for (hipEvent_t *ev : {&sl.ev_in, &sl.ev_comp, &sl.ev_out})
+            if (e == hipSuccess)
+                e = make_event(*ev);
+    for (hipEvent_t &ev : h.ev_read)
         if (e == hipSuccess)
-            e = hipStreamCreateWithFlags(&h.s_comp, hipStreamNonBlocking);
-        if (e == hipSuccess)
-            e = hipStreamCreateWithFlags(&h.s_out, hipStreamNonBlocking);
-        if (e != hipSuccess)
-            return e;
-    }
-    while (h.ev_in.size() < chunks) {
-        hipEvent_t a = nullptr, b = nullptr;
-        e = hipEventCreateWithFlags(&a, hipEventDisableTiming);
-        if (e != hipSuccess)
-            return e;
-        e = hipEventCreateWithFlags(&b, hipEventDisableTiming);
-        if (e != hipSuccess) {
-            (void)hipEventDestroy(a);
-            return e;
-        }
-        h.ev_in.push_back(a);
-        h.ev_comp.push_back(b);
-    }
-    // Up to 4 bytes past the last read byte may be touched by aligned loads.
-    if (ascii_bytes + 64 > h.ascii_cap) {
-        h.ascii_cap = 0;
-        if ((e = realloc_device(h.ascii, ascii_bytes + 64)) != hipSuccess)
-            return e;
-        h.ascii_cap = ascii_bytes + 64;
-    }
-    if (n_reads > h.read_cap || h.off == nullptr) {
-        h.read_cap = 0;
-        if ((e = realloc_device(h.off, n_reads + 1)) != hipSuccess ||
-            (e = realloc_device(h.len, n_reads)) != hipSuccess ||
-            (e = realloc_device(h.has_n, n_reads)) != hipSuccess)
-            return e;
-        h.read_cap = n_reads;
-    }
-    if (packed_words > h.packed_cap || h.packed == nullptr) {
-        h.packed_cap = 0;
-        if ((e = realloc_device(h.packed, packed_words)) != hipSuccess)
-            return e;
-        h.packed_cap = packed_words;
-    }
-    if (n_pairs > h.pair_cap || h.cand_pos == nullptr) {
-        h.pair_cap = 0;
-        if ((e = realloc_device(h.pair_read, n_pairs)) != hipSuccess ||
-            (e = realloc_device(h.cand_pos, n_pairs)) != hipSuccess ||
-            (e = realloc_device(h.e, n_pairs)) != hipSuccess ||
-            (e = realloc_device(h.accept, n_pairs)) != hipSuccess ||
-            (e = realloc_device(h.est, n_pairs)) != hipSuccess)
-            return e;
-        h.pair_cap = n_pairs;
-    }
-    return hipSuccess;
+            e = make_event(ev);
+    return e;
+}
+
+// Pairs per chunk: the option, else n_pairs / 16 within [2^20, 2^22]; never
+// more than the batch; a multiple of 64.
+uint64_t chunk_pairs(const gk_ctx *ctx, uint64_t np)
+{
+    uint64_t p = ctx->host_chunk_pairs;
+    if (p == 0)
+        p = std::min<uint64_t>(1u << 22, std::max<uint64_t>(1u << 20, (np + 15) / 16));
+    p = std::min(p, np);
+    return (p + 63) / 64 * 64;
 }
 
 }  // namespace
@@ -103,23 +109,25 @@ hipError_t ensure_buffers(HostPipe &h, uint64_t ascii_bytes, uint64_t n_reads,
 void gk_detail_free_host_pipe(gk_ctx *ctx)
 {
     HostPipe &h = ctx->host;
-    release(h.ascii);
-    release(h.off);
-    release(h.packed);
-    release(h.len);
-    release(h.has_n);
-    release(h.pair_read);
-    release(h.cand_pos);
-    release(h.e);
-    release(h.accept);
-    release(h.est);
-    h.ascii_cap = h.read_cap = h.packed_cap = h.pair_cap = 0;
-    for (hipEvent_t ev : h.ev_in)
-        (void)hipEventDestroy(ev);
-    for (hipEvent_t ev : h.ev_comp)
-        (void)hipEventDestroy(ev);
-    h.ev_in.clear();
-    h.ev_comp.clear();
+    release(h.all);
+    for (HostSlot &sl : h.slot) {
+        release(sl.reads);
+        release(sl.pair_read);
+        release(sl.cand_pos);
+        release(sl.e);
+        release(sl.accept);
+        release(sl.est);
+        for (hipEvent_t *ev : {&sl.ev_in, &sl.ev_comp, &sl.ev_out}) {
+            if (*ev)
+                (void)hipEventDestroy(*ev);
+            *ev = nullptr;
+        }
+    }
+    for (hipEvent_t &ev : h.ev_read) {
+        if (ev)
+            (void)hipEventDestroy(ev);
+        ev = nullptr;
+    }
     for (uint8_t *&st : h.stage) {
         if (st)
             (void)hipHostFree(st);
@@ -176,24 +184,66 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         return fail(ctx, GK_EDEVICE, "gk_filter_host: hipSetDevice failed");
 
     const uint64_t nr = b->n_reads, np = b->n_pairs;
-    const uint32_t pitch = (uint32_t)std::max<uint64_t>(64, (nr + 63) / 64 * 64);
     const uint32_t rows = (b->max_read_len + 15) / 16;
     // ASCII reads encoded here on host threads (GK_OPT_HOST_ENCODE_THREADS):
     // 2-bit rows cross the bus, as for reads the caller encoded.
     const bool encode_here = !host_encoded && ctx->host_encode_threads > 0 && nr > 0;
     const bool rows_in = host_encoded || encode_here;
     const uint64_t text_bytes = (!host_encoded && nr) ? b->read_off[nr] : 0;
-    // ASCII text, or 2-bit rows staged in the same buffer.
-    const uint64_t bytes = rows_in ? nr * rows * sizeof(uint32_t) : text_bytes;
     const bool identity = b->pair_read == nullptr;
+    constexpr uint32_t S = HostPipe::SLOTS;
 
-    // Chunks of at least 2^20 pairs, at most 16 of them.
-    const uint32_t K = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, (np + (1u << 20) - 1) >> 20));
-    const uint64_t P = ((np + K - 1) / K + 63) / 64 * 64;           // pairs per chunk
-    const uint64_t R = identity ? P : std::max<uint64_t>(1, (nr + K - 1) / K);  // reads per chunk
+    // Pair chunks of P pairs.  With pair i using read i, read chunk j is the
+    // reads of pair chunk j and lives in slot j % S beside it; otherwise every
+    // read stays resident (any pair may use any read), copied and encoded in
+    // up to 16 chunks of R reads, and a pair chunk is filtered once the read
+    // chunks holding its reads are encoded.
+    const uint64_t P = chunk_pairs(ctx, np);
+    const uint64_t K = (np + P - 1) / P;
+    const uint64_t Kr = identity ? K : std::min<uint64_t>(K, 16);
+    const uint64_t R = identity ? P : std::max<uint64_t>(1, (nr + Kr - 1) / Kr);
+    // Transposed read words: pitch P in a slot, or every read in `all`.
+    const uint32_t pitch =
+        identity ? (uint32_t)P : (uint32_t)std::max<uint64_t>(64, (nr + 63) / 64 * 64);
 
     HostPipe &h = ctx->host;
-    hipError_t e = ensure_buffers(h, bytes, nr, (uint64_t)rows * pitch, np, K);
+    hipError_t e = ensure_streams(h);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "streams and events");
+    if (identity) {
+        // A slot holds one read chunk's text from the 64-byte boundary at or
+        // below its first offset, and 64 bytes of slack for aligned loads.
+        uint64_t slot_text = 0;
+        if (rows_in) {
+            slot_text = P * rows * sizeof(uint32_t);
+        } else {
+            for (uint64_t j = 0; j < K; ++j) {
+                const uint64_t r0 = std::min(nr, j * R), r1 = std::min(nr, r0 + R);
+                const uint64_t a0 = b->read_off[r0] & ~63ull;
+                const uint64_t a1 = std::min(b->read_off[r1], text_bytes);
+                if (a1 > a0)
+                    slot_text = std::max(slot_text, a1 - a0);
+            }
+            slot_text += 64;
+        }
+        for (uint32_t i = 0; i < S && i < K && e == hipSuccess; ++i)
+            e = fit(h.slot[i].reads, slot_text, P, (uint64_t)rows * P);
+    } else {
+        e = fit(h.all, rows_in ? nr * rows * sizeof(uint32_t) : text_bytes + 64, nr,
+                (uint64_t)rows * pitch);
+    }
+    for (uint32_t i = 0; i < S && i < K && e == hipSuccess; ++i) {
+        HostSlot &sl = h.slot[i];
+        e = fit(sl.cand_pos, P);
+        if (e == hipSuccess && !identity)
+            e = fit(sl.pair_read, P);
+        if (e == hipSuccess && b->e)
+            e = fit(sl.e, P);
+        if (e == hipSuccess)
+            e = fit(sl.accept, P);
+        if (e == hipSuccess)
+            e = fit(sl.est, P);
+    }
     if (e != hipSuccess)
         return hip_fail(ctx, e, "device buffers");
     // Two pinned staging buffers, each one read chunk of rows, lengths and
@@ -210,8 +260,7 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
             }
             h.stage_cap = 0;
             for (uint8_t *&st : h.stage)
-                if ((e = gk_hmalloc((void **)&st, stage_bytes)) !=
-                    hipSuccess)
+                if ((e = gk_hmalloc((void **)&st, stage_bytes)) != hipSuccess)
                     return hip_fail(ctx, e, "pinned staging");
             h.stage_cap = stage_bytes;
         }
@@ -222,29 +271,110 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         }
     }
 
-    std::vector<uint32_t> need(K, 0);   // last read chunk each pair chunk needs
+    // Last read chunk pair chunk q needs (found when q is first considered).
+    std::vector<int64_t> need(K, -1);
+    auto need_of = [&](uint64_t q) -> uint64_t {
+        if (need[q] < 0) {
+            if (identity) {
+                need[q] = (int64_t)q;
+            } else {
+                const uint64_t q0 = q * P, q1 = std::min(np, q0 + P);
+                uint32_t mx = 0;
+                for (uint64_t i = q0; i < q1; ++i) {
+                    const uint32_t r = b->pair_read[i];
+                    if (r < nr && r > mx)
+                        mx = r;          // pairs of reads >= n_reads are GK_INVALID
+                }
+                need[q] = (int64_t)std::min<uint64_t>(Kr - 1, nr ? mx / R : 0);
+            }
+        }
+        return (uint64_t)need[q];
+    };
+
+    // Pair chunk q: copies in, filter, copies out, in slot q % S.  Returns a
+    // library status; hip errors land in e.
+    auto run_pairs = [&](uint64_t q) -> int {
+        HostSlot &sl = h.slot[q % S];
+        const uint64_t q0 = q * P, q1 = std::min(np, q0 + P), n = q1 - q0;
+        if (q >= S)          // the slot's inputs are free once chunk q - S is filtered
+            e = hipStreamWaitEvent(h.s_in, sl.ev_comp, 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sl.cand_pos.p, b->cand_pos + q0, n * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, h.s_in);
+        if (e == hipSuccess && b->e)
+            e = hipMemcpyAsync(sl.e.p, b->e + q0, n, hipMemcpyHostToDevice, h.s_in);
+        if (e == hipSuccess && !identity)
+            e = hipMemcpyAsync(sl.pair_read.p, b->pair_read + q0, n * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, h.s_in);
+        if (e == hipSuccess)
+            e = hipEventRecord(sl.ev_in, h.s_in);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(h.s_comp, sl.ev_in, 0);
+        if (e == hipSuccess && q >= S)   // ... and its outputs once q - S is copied out
+            e = hipStreamWaitEvent(h.s_comp, sl.ev_out, 0);
+        if (e != hipSuccess)
+            return GK_OK;
+        gk_batch fb{};
+        fb.pitch = pitch;
+        fb.max_read_len = b->max_read_len;
+        fb.e_uniform = b->e_uniform;
+        fb.read_layout = host_encoded ? b->packed_layout : GK_READS_SPLIT;   // encode_here: split
+        fb.flags = b->flags;
+        fb.n_pairs = n;
+        fb.cand_pos = sl.cand_pos.p;
+        fb.e = b->e ? sl.e.p : nullptr;
+        fb.accept = sl.accept.p;
+        fb.est = sl.est.p;
+        const HostReads &rd = identity ? sl.reads : h.all;
+        fb.n_reads = identity ? (uint32_t)n : (uint32_t)nr;   // pair i of the chunk: read i
+        fb.reads = rd.packed.p;
+        fb.read_len = rd.len.p;
+        fb.read_has_n = rd.has_n.p;
+        fb.pair_read = identity ? nullptr : sl.pair_read.p;
+        const int st = gk_filter(ctx, &fb, h.s_comp);
+        if (st != GK_OK)
+            return st;
+        e = hipEventRecord(sl.ev_comp, h.s_comp);
+        if (e == hipSuccess)
+            e = hipStreamWaitEvent(h.s_out, sl.ev_comp, 0);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->accept + q0, sl.accept.p, n, hipMemcpyDeviceToHost, h.s_out);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->est + q0, sl.est.p, n * sizeof(uint16_t),
+                               hipMemcpyDeviceToHost, h.s_out);
+        if (e == hipSuccess)
+            e = hipEventRecord(sl.ev_out, h.s_out);
+        return GK_OK;
+    };
+
+    int status = GK_OK;
     bool bad_offsets = false;
-    uint32_t next_q = 0;
-    for (uint32_t j = 0; j < K && e == hipSuccess; ++j) {
-        // Read chunk j: offsets must be non-decreasing and within the text.
-        const uint64_t r0 = std::min<uint64_t>(nr, (uint64_t)j * R);
-        const uint64_t r1 = std::min<uint64_t>(nr, r0 + R);
+    uint64_t next_q = 0;
+    for (uint64_t j = 0; j < Kr && e == hipSuccess && status == GK_OK; ++j) {
+        // Read chunk j, into slot j % S (one pair per read) or into `all`.
+        const uint64_t r0 = std::min(nr, j * R), r1 = std::min(nr, r0 + R), cnt = r1 - r0;
+        HostReads &rd = identity ? h.slot[j % S].reads : h.all;
+        const uint64_t at = identity ? 0 : r0;     // rd's index of read r0
+        if (identity && j >= S)    // slot free once chunk j - S is filtered
+            e = hipStreamWaitEvent(h.s_in, h.slot[j % S].ev_comp, 0);
         uint32_t *rows_dev =
-            rows_in ? reinterpret_cast<uint32_t *>(h.ascii) + r0 * rows : nullptr;
-        if (r1 > r0 && encode_here) {
+            rows_in ? reinterpret_cast<uint32_t *>(rd.text.p) + at * rows : nullptr;
+        uint64_t text_base = 0;
+        if (e != hipSuccess || cnt == 0) {
+            // nothing to copy (no reads left, or an error to report)
+        } else if (encode_here) {
             for (uint64_t r = r0; r < r1 && !bad_offsets; ++r)
                 bad_offsets = b->read_off[r + 1] < b->read_off[r];
             bad_offsets = bad_offsets || b->read_off[r1] > text_bytes;
             if (bad_offsets)
                 break;
             if (j >= 2)
-                e = hipEventSynchronize(h.ev_in[j - 2]);
+                e = hipEventSynchronize(h.ev_read[j & 1u]);
             uint8_t *st = h.stage[j & 1u];
             uint32_t *rows_h = reinterpret_cast<uint32_t *>(st);
             uint16_t *len_h = reinterpret_cast<uint16_t *>(st + stage_rows_bytes);
             uint8_t *has_n_h = st + stage_rows_bytes + R * sizeof(uint16_t);
             if (e == hipSuccess) {
-                const uint64_t cnt = r1 - r0;
                 h.pool->run([&](unsigned i, unsigned n) {
                     const uint64_t a = r0 + cnt * i / n, z = r0 + cnt * (i + 1) / n;
                     gkd::host_encode_rows(b->ascii, text_bytes, b->read_off, a, z, rows,
@@ -255,123 +385,63 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
                                    hipMemcpyHostToDevice, h.s_in);
             }
             if (e == hipSuccess)
-                e = hipMemcpyAsync(h.len + r0, len_h, (r1 - r0) * sizeof(uint16_t),
+                e = hipMemcpyAsync(rd.len.p + at, len_h, cnt * sizeof(uint16_t),
                                    hipMemcpyHostToDevice, h.s_in);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(h.has_n + r0, has_n_h, r1 - r0, hipMemcpyHostToDevice,
-                                   h.s_in);
-        } else if (r1 > r0 && host_encoded) {
-            e = hipMemcpyAsync(rows_dev, b->packed + r0 * rows,
-                               (r1 - r0) * rows * sizeof(uint32_t), hipMemcpyHostToDevice,
-                               h.s_in);
+                e = hipMemcpyAsync(rd.has_n.p + at, has_n_h, cnt, hipMemcpyHostToDevice, h.s_in);
+        } else if (host_encoded) {
+            e = hipMemcpyAsync(rows_dev, b->packed + r0 * rows, cnt * rows * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, h.s_in);
             if (e == hipSuccess)
-                e = hipMemcpyAsync(h.len + r0, b->read_len + r0, (r1 - r0) * sizeof(uint16_t),
+                e = hipMemcpyAsync(rd.len.p + at, b->read_len + r0, cnt * sizeof(uint16_t),
                                    hipMemcpyHostToDevice, h.s_in);
             if (e == hipSuccess)
                 e = b->read_has_n
-                        ? hipMemcpyAsync(h.has_n + r0, b->read_has_n + r0, r1 - r0,
+                        ? hipMemcpyAsync(rd.has_n.p + at, b->read_has_n + r0, cnt,
                                          hipMemcpyHostToDevice, h.s_in)
-                        : hipMemsetAsync(h.has_n + r0, 0, r1 - r0, h.s_in);
-        } else if (r1 > r0) {
+                        : hipMemsetAsync(rd.has_n.p + at, 0, cnt, h.s_in);
+        } else {
             for (uint64_t r = r0; r < r1 && !bad_offsets; ++r)
                 bad_offsets = b->read_off[r + 1] < b->read_off[r];
-            bad_offsets = bad_offsets || b->read_off[r1] > bytes;
+            bad_offsets = bad_offsets || b->read_off[r1] > text_bytes;
             if (bad_offsets)
                 break;
-            const uint64_t a0 = b->read_off[r0], a1 = b->read_off[r1];
+            // The chunk's text: in a slot from the 64-byte boundary at or
+            // below its first offset; in `all` at its own offsets.
+            const uint64_t a0 = identity ? b->read_off[r0] & ~63ull : b->read_off[r0];
+            const uint64_t a1 = b->read_off[r1];
+            text_base = identity ? a0 : 0;
             if (a1 > a0)
-                e = hipMemcpyAsync(h.ascii + a0, b->ascii + a0, a1 - a0, hipMemcpyHostToDevice,
-                                   h.s_in);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(h.off + r0, b->read_off + r0, (r1 - r0 + 1) * sizeof(uint64_t),
+                e = hipMemcpyAsync(rd.text.p + (a0 - text_base), b->ascii + a0, a1 - a0,
                                    hipMemcpyHostToDevice, h.s_in);
-        }
-        // Pair chunk j.
-        const uint64_t p0 = std::min<uint64_t>(np, (uint64_t)j * P);
-        const uint64_t p1 = std::min<uint64_t>(np, p0 + P);
-        if (e == hipSuccess && p1 > p0) {
-            e = hipMemcpyAsync(h.cand_pos + p0, b->cand_pos + p0, (p1 - p0) * sizeof(uint32_t),
-                               hipMemcpyHostToDevice, h.s_in);
-            if (e == hipSuccess && b->e)
-                e = hipMemcpyAsync(h.e + p0, b->e + p0, p1 - p0, hipMemcpyHostToDevice, h.s_in);
-            if (e == hipSuccess && !identity)
-                e = hipMemcpyAsync(h.pair_read + p0, b->pair_read + p0,
-                                   (p1 - p0) * sizeof(uint32_t), hipMemcpyHostToDevice, h.s_in);
-        }
-        if (!identity && p1 > p0 && nr > 0) {
-            uint32_t mx = 0;
-            for (uint64_t i = p0; i < p1; ++i) {
-                const uint32_t r = b->pair_read[i];
-                if (r < nr && r > mx)
-                    mx = r;          // pairs of reads >= n_reads are GK_INVALID
-            }
-            need[j] = (uint32_t)std::min<uint64_t>(K - 1, mx / R);
-        } else {
-            need[j] = j;
+            // Offsets r0 .. r1; in `all`, offset r0 came with the previous
+            // chunk, whose encoding may still be reading it.
+            const uint64_t o0 = (identity || j == 0) ? r0 : r0 + 1;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(rd.off.p + at + (o0 - r0), b->read_off + o0,
+                                   (r1 + 1 - o0) * sizeof(uint64_t), hipMemcpyHostToDevice,
+                                   h.s_in);
         }
         if (e == hipSuccess)
-            e = hipEventRecord(h.ev_in[j], h.s_in);
+            e = hipEventRecord(h.ev_read[j & 1u], h.s_in);
         if (e == hipSuccess)
-            e = hipStreamWaitEvent(h.s_comp, h.ev_in[j], 0);
-        if (e == hipSuccess && r1 > r0)
-            e = rows_in
-                    ? gkd::launch_transpose_reads(rows_dev, (uint32_t)(r1 - r0), rows, pitch,
-                                                  h.packed + r0, h.s_comp)
-                    : gkd::launch_encode_reads(h.ascii, h.off + r0, (uint32_t)(r1 - r0), pitch,
-                                               rows, GK_READS_SPLIT, h.packed + r0, h.len + r0,
-                                               h.has_n + r0, h.s_comp);
-        // Filter every pair chunk whose reads are now encoded, in order.
-        while (e == hipSuccess && next_q <= j && need[next_q] <= j) {
-            const uint32_t q = next_q++;
-            const uint64_t q0 = std::min<uint64_t>(np, (uint64_t)q * P);
-            const uint64_t q1 = std::min<uint64_t>(np, q0 + P);
-            if (q1 == q0)
-                continue;
-            gk_batch fb{};
-            fb.pitch = pitch;
-            fb.max_read_len = b->max_read_len;
-            fb.e_uniform = b->e_uniform;
-            fb.read_layout = host_encoded ? b->packed_layout : GK_READS_SPLIT;   // encode_here: split
-            fb.flags = b->flags;
-            fb.n_pairs = q1 - q0;
-            fb.cand_pos = h.cand_pos + q0;
-            fb.e = b->e ? h.e + q0 : nullptr;
-            fb.accept = h.accept + q0;
-            fb.est = h.est + q0;
-            if (identity) {            // pair i of the chunk uses read q0 + i
-                fb.n_reads = (uint32_t)(q1 - q0);
-                fb.reads = h.packed + q0;
-                fb.read_len = h.len + q0;
-                fb.read_has_n = h.has_n + q0;
-                fb.pair_read = nullptr;
-            } else {
-                fb.n_reads = (uint32_t)nr;
-                fb.reads = h.packed;
-                fb.read_len = h.len;
-                fb.read_has_n = h.has_n;
-                fb.pair_read = h.pair_read + q0;
-            }
-            const int st = gk_filter(ctx, &fb, h.s_comp);
-            if (st != GK_OK) {
-                (void)hipStreamSynchronize(h.s_in);
-                (void)hipStreamSynchronize(h.s_comp);
-                (void)hipStreamSynchronize(h.s_out);
-                return st;
-            }
-            e = hipEventRecord(h.ev_comp[q], h.s_comp);
-            if (e == hipSuccess)
-                e = hipStreamWaitEvent(h.s_out, h.ev_comp[q], 0);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(b->accept + q0, h.accept + q0, q1 - q0, hipMemcpyDeviceToHost,
-                                   h.s_out);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(b->est + q0, h.est + q0, (q1 - q0) * sizeof(uint16_t),
-                                   hipMemcpyDeviceToHost, h.s_out);
-        }
+            e = hipStreamWaitEvent(h.s_comp, h.ev_read[j & 1u], 0);
+        if (e == hipSuccess && cnt > 0)
+            e = rows_in ? gkd::launch_transpose_reads(rows_dev, (uint32_t)cnt, rows, pitch,
+                                                      rd.packed.p + at, h.s_comp)
+                        : gkd::launch_encode_reads(rd.text.p, rd.off.p + at, (uint32_t)cnt, pitch,
+                                                   rows, GK_READS_SPLIT, rd.packed.p + at,
+                                                   rd.len.p + at, rd.has_n.p + at, h.s_comp,
+                                                   text_base);
+        // Every pair chunk whose reads are now encoded, in order.
+        while (e == hipSuccess && status == GK_OK && next_q < K && need_of(next_q) <= j)
+            status = run_pairs(next_q++);
     }
     const hipError_t e1 = hipStreamSynchronize(h.s_in);
     const hipError_t e2 = hipStreamSynchronize(h.s_comp);
     const hipError_t e3 = hipStreamSynchronize(h.s_out);
+    if (status != GK_OK)
+        return status;
     if (e == hipSuccess)
         e = e1 != hipSuccess ? e1 : (e2 != hipSuccess ? e2 : e3);
     if (e != hipSuccess)

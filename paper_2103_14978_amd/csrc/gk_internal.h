@@ -20,24 +20,45 @@ struct MixedConfig {
     uint32_t blocks_per_cu = 0;   // persistent grid: 0 = as many as fit
 };
 
-// Device buffers and streams of gk_filter_host, grown on demand and kept.
+// A device buffer of gk_filter_host and its capacity in elements.
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    uint64_t cap = 0;
+};
+
+// Reads on the device: their text (or host-encoded row-major words), offsets,
+// lengths, unknown-base flags and transposed 2-bit words.
+struct HostReads {
+    DevBuf<uint8_t> text;
+    DevBuf<uint64_t> off;
+    DevBuf<uint16_t> len;
+    DevBuf<uint8_t> has_n;
+    DevBuf<uint32_t> packed;
+};
+
+// One chunk of gk_filter_host in flight: its pairs and results, and, when
+// pair i uses read i, its reads.  ev_in: its copies in are done; ev_comp: its
+// filter is done (inputs free); ev_out: its results are copied out (outputs
+// free).
+struct HostSlot {
+    HostReads reads;
+    DevBuf<uint32_t> pair_read, cand_pos;
+    DevBuf<uint8_t> e, accept;
+    DevBuf<uint16_t> est;
+    hipEvent_t ev_in = nullptr, ev_comp = nullptr, ev_out = nullptr;
+};
+
+// Device buffers and streams of gk_filter_host, grown on demand and kept:
+// SLOTS chunks in flight (copies in, filter, copies out), so device memory is
+// bounded by the chunk size, plus every read of a batch whose pairs name
+// their reads (any pair may use any read).
 struct HostPipe {
+    static constexpr uint32_t SLOTS = 3;
     hipStream_t s_in = nullptr, s_comp = nullptr, s_out = nullptr;
-    uint8_t *ascii = nullptr;
-    uint64_t ascii_cap = 0;      // bytes (or host-encoded row-major words)
-    uint64_t *off = nullptr;
-    uint32_t *packed = nullptr;
-    uint16_t *len = nullptr;
-    uint8_t *has_n = nullptr;
-    uint64_t read_cap = 0;       // reads (off holds read_cap + 1 entries)
-    uint64_t packed_cap = 0;     // words
-    uint32_t *pair_read = nullptr;
-    uint32_t *cand_pos = nullptr;
-    uint8_t *e = nullptr;
-    uint8_t *accept = nullptr;
-    uint16_t *est = nullptr;
-    uint64_t pair_cap = 0;       // pairs
-    std::vector<hipEvent_t> ev_in, ev_comp;
+    HostSlot slot[SLOTS];
+    HostReads all;
+    hipEvent_t ev_read[2] = {nullptr, nullptr};   // read chunk j's copies: [j % 2]
     uint8_t *stage[2] = {nullptr, nullptr};   // pinned: host-encoded read chunks
     uint64_t stage_cap = 0;      // bytes of each
     std::unique_ptr<gkd::HostEncodePool> pool;  // host encoding threads
@@ -61,6 +82,7 @@ struct gk_ctx {
     MixedConfig mixed;
     uint32_t use_graph = 1;                   // GK_OPT_MIXED_GRAPH
     uint32_t host_encode_threads = 0;         // GK_OPT_HOST_ENCODE_THREADS
+    uint64_t host_chunk_pairs = 0;            // GK_OPT_HOST_CHUNK_PAIRS (0: automatic)
     uint64_t server_part_pairs = 1u << 17;    // GK_OPT_SERVER_PART_PAIRS
     uint64_t server_tick_pairs = 1u << 20;    // GK_OPT_SERVER_TICK_PAIRS
     uint32_t *d_mixed_counters = nullptr;     // [tile counter, residual count]
@@ -163,9 +185,12 @@ size_t mixed_lds_size(uint32_t tile);
 hipError_t launch_filter(const FilterArgs &a, uint32_t words, uint32_t layout,
                          uint32_t pairs_per_lane, hipStream_t s);
 
+// Text offset t of read_off is at ascii[t - text_base]; text_base must not
+// exceed read_off[0] (a chunk's text copied to the start of a buffer).
 hipError_t launch_encode_reads(const uint8_t *ascii, const uint64_t *read_off, uint32_t n_reads,
                                uint32_t pitch, uint32_t rows, uint32_t layout, uint32_t *packed,
-                               uint16_t *len_out, uint8_t *has_n_out, hipStream_t s);
+                               uint16_t *len_out, uint8_t *has_n_out, hipStream_t s,
+                               uint64_t text_base = 0);
 
 // Host-encoded reads, rows words per read in read order, to the transposed
 // layout: out[w * pitch + r] = rowmajor[r * rows + w] for r < n_reads.

@@ -37,280 +37,13 @@
 
 extern "C" int gk_detail_server_inject_failure(gk_server *s, uint64_t load_at, uint64_t tick_at);
 
-// ---- stand-in HIP runtime ---------------------------------------------------
+#include "standin_hip.h"
 
 namespace {
 
 std::atomic<int> g_bad_table{0};      // a tick table inconsistent with its parts
 
-struct Op {
-    std::function<void()> fn;
-};
-
 }  // namespace
-
-struct ihipStream_t {
-    std::mutex mu;
-    std::condition_variable cv;
-    std::deque<Op> q;
-    uint64_t enqueued = 0, done = 0;
-    bool stop = false;
-    bool capturing = false;
-    std::vector<Op> captured;
-    std::thread worker;
-
-    ihipStream_t()
-    {
-        worker = std::thread([this] {
-            std::unique_lock<std::mutex> lk(mu);
-            while (true) {
-                cv.wait(lk, [&] { return stop || !q.empty(); });
-                if (q.empty() && stop)
-                    return;
-                Op op = std::move(q.front());
-                q.pop_front();
-                lk.unlock();
-                op.fn();
-                lk.lock();
-                done++;
-                cv.notify_all();
-            }
-        });
-    }
-    ~ihipStream_t()
-    {
-        {
-            std::lock_guard<std::mutex> lk(mu);
-            stop = true;
-            cv.notify_all();
-        }
-        worker.join();
-    }
-    void enqueue(std::function<void()> fn)
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        if (capturing) {
-            captured.push_back(Op{std::move(fn)});
-            return;
-        }
-        q.push_back(Op{std::move(fn)});
-        enqueued++;
-        cv.notify_all();
-    }
-    void sync()
-    {
-        std::unique_lock<std::mutex> lk(mu);
-        const uint64_t target = enqueued;
-        cv.wait(lk, [&] { return done >= target; });
-    }
-};
-
-// An event's state outlives its handle while stream operations still refer
-// to it (as the runtime allows destroying an event that is still pending).
-struct EventState {
-    std::mutex mu;
-    std::condition_variable cv;
-    uint64_t recorded = 0, fired = 0;   // generations
-};
-
-struct ihipEvent_t {
-    std::shared_ptr<EventState> st = std::make_shared<EventState>();
-};
-
-struct ihipGraph {
-    std::vector<Op> ops;
-};
-
-struct hipGraphExec {
-    std::vector<Op> ops;
-};
-
-namespace {
-
-void event_wait(const std::shared_ptr<EventState> &ev, uint64_t gen)
-{
-    std::unique_lock<std::mutex> lk(ev->mu);
-    ev->cv.wait(lk, [&] { return ev->fired >= gen; });
-}
-
-}  // namespace
-
-extern "C" {
-
-hipError_t hipStreamCreateWithFlags(hipStream_t *s, unsigned int)
-{
-    *s = new ihipStream_t();
-    return hipSuccess;
-}
-
-hipError_t hipStreamDestroy(hipStream_t s)
-{
-    delete s;
-    return hipSuccess;
-}
-
-hipError_t hipStreamSynchronize(hipStream_t s)
-{
-    s->sync();
-    return hipSuccess;
-}
-
-hipError_t hipEventCreateWithFlags(hipEvent_t *ev, unsigned int)
-{
-    *ev = new ihipEvent_t();
-    return hipSuccess;
-}
-
-hipError_t hipEventDestroy(hipEvent_t ev)
-{
-    delete ev;
-    return hipSuccess;
-}
-
-hipError_t hipEventRecord(hipEvent_t ev, hipStream_t s)
-{
-    std::shared_ptr<EventState> st = ev->st;
-    uint64_t gen;
-    {
-        std::lock_guard<std::mutex> lk(st->mu);
-        gen = ++st->recorded;
-    }
-    s->enqueue([st, gen] {
-        std::lock_guard<std::mutex> lk(st->mu);
-        if (st->fired < gen)
-            st->fired = gen;
-        st->cv.notify_all();
-    });
-    return hipSuccess;
-}
-
-hipError_t hipEventSynchronize(hipEvent_t ev)
-{
-    uint64_t gen;
-    {
-        std::lock_guard<std::mutex> lk(ev->st->mu);
-        gen = ev->st->recorded;
-    }
-    event_wait(ev->st, gen);
-    return hipSuccess;
-}
-
-hipError_t hipStreamWaitEvent(hipStream_t s, hipEvent_t ev, unsigned int)
-{
-    std::shared_ptr<EventState> st = ev->st;
-    uint64_t gen;
-    {
-        std::lock_guard<std::mutex> lk(st->mu);
-        gen = st->recorded;
-    }
-    s->enqueue([st, gen] { event_wait(st, gen); });
-    return hipSuccess;
-}
-
-hipError_t hipMemcpyAsync(void *dst, const void *src, size_t n, hipMemcpyKind, hipStream_t s)
-{
-    s->enqueue([dst, src, n] { std::memcpy(dst, src, n); });
-    return hipSuccess;
-}
-
-hipError_t hipStreamBeginCapture(hipStream_t s, hipStreamCaptureMode)
-{
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->capturing = true;
-    s->captured.clear();
-    return hipSuccess;
-}
-
-hipError_t hipStreamEndCapture(hipStream_t s, hipGraph_t *g)
-{
-    std::lock_guard<std::mutex> lk(s->mu);
-    s->capturing = false;
-    auto *graph = new ihipGraph();
-    graph->ops = std::move(s->captured);
-    s->captured.clear();
-    *g = graph;
-    return hipSuccess;
-}
-
-hipError_t hipGraphInstantiate(hipGraphExec_t *exec, hipGraph_t g, hipGraphNode_t *, char *,
-                               size_t)
-{
-    auto *x = new hipGraphExec();
-    x->ops = g->ops;
-    *exec = x;
-    return hipSuccess;
-}
-
-hipError_t hipGraphDestroy(hipGraph_t g)
-{
-    delete g;
-    return hipSuccess;
-}
-
-hipError_t hipGraphExecDestroy(hipGraphExec_t x)
-{
-    delete x;
-    return hipSuccess;
-}
-
-hipError_t hipGraphLaunch(hipGraphExec_t x, hipStream_t s)
-{
-    for (const Op &op : x->ops)
-        s->enqueue(op.fn);
-    return hipSuccess;
-}
-
-hipError_t hipFree(void *p)
-{
-    std::free(p);
-    return hipSuccess;
-}
-
-hipError_t hipHostFree(void *p)
-{
-    std::free(p);
-    return hipSuccess;
-}
-
-hipError_t hipSetDevice(int) { return hipSuccess; }
-
-hipError_t hipGetDevice(int *d)
-{
-    *d = 0;
-    return hipSuccess;
-}
-
-const char *hipGetErrorName(hipError_t e)
-{
-    return e == hipSuccess ? "hipSuccess" : "hipError (stand-in)";
-}
-
-}  // extern "C"
-
-namespace {
-
-void *zalloc(size_t bytes)
-{
-    const size_t n = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
-    void *p = std::aligned_alloc(256, n);
-    if (p)
-        std::memset(p, 0, n);
-    return p;
-}
-
-}  // namespace
-
-hipError_t gk_detail_device_alloc(void **p, size_t bytes)
-{
-    *p = zalloc(bytes);
-    return *p ? hipSuccess : hipErrorOutOfMemory;
-}
-
-hipError_t gk_detail_pinned_alloc(void **p, size_t bytes)
-{
-    *p = zalloc(bytes);
-    return *p ? hipSuccess : hipErrorOutOfMemory;
-}
 
 // ---- stand-in kernels -------------------------------------------------------
 
@@ -350,12 +83,13 @@ namespace gkd {
 
 hipError_t launch_encode_reads(const uint8_t *ascii, const uint64_t *read_off, uint32_t n_reads,
                                uint32_t pitch, uint32_t rows, uint32_t, uint32_t *packed,
-                               uint16_t *len_out, uint8_t *has_n_out, hipStream_t s)
+                               uint16_t *len_out, uint8_t *has_n_out, hipStream_t s,
+                               uint64_t text_base)
 {
     s->enqueue([=] {
         for (uint32_t r = 0; r < n_reads; ++r) {
             const uint64_t len = read_off[r + 1] - read_off[r];
-            packed[r] = text_hash(ascii + read_off[r], len);
+            packed[r] = text_hash(ascii + (read_off[r] - text_base), len);
             for (uint32_t w = 1; w < rows; ++w)
                 packed[(size_t)w * pitch + r] = 0;
             len_out[r] = (uint16_t)len;

@@ -95,7 +95,9 @@ def test_errors(gkctx):
         assert ei.value.status == gk.GK_EINVAL
         for opt, val in ((gk.GK_OPT_PAIRS_PER_LANE, -1), (gk.GK_OPT_PAIRS_PER_LANE, 65537),
                          (gk.GK_OPT_HOST_ENCODE_THREADS, -1),
-                         (gk.GK_OPT_HOST_ENCODE_THREADS, 65), (999, 0)):
+                         (gk.GK_OPT_HOST_ENCODE_THREADS, 65),
+                         (gk.GK_OPT_HOST_CHUNK_PAIRS, 63),
+                         (gk.GK_OPT_HOST_CHUNK_PAIRS, (1 << 26) + 1), (999, 0)):
             with pytest.raises(gk.GkError) as ei:
                 gk.gk_set_option(ctx2, opt, val)
             assert ei.value.status == gk.GK_EINVAL
@@ -104,6 +106,9 @@ def test_errors(gkctx):
         assert gk.gk_get_option(ctx2, gk.GK_OPT_HOST_ENCODE_THREADS) == 0
         gk.gk_set_option(ctx2, gk.GK_OPT_HOST_ENCODE_THREADS, 64)
         assert gk.gk_get_option(ctx2, gk.GK_OPT_HOST_ENCODE_THREADS) == 64
+        assert gk.gk_get_option(ctx2, gk.GK_OPT_HOST_CHUNK_PAIRS) == 0
+        gk.gk_set_option(ctx2, gk.GK_OPT_HOST_CHUNK_PAIRS, 1 << 26)
+        assert gk.gk_get_option(ctx2, gk.GK_OPT_HOST_CHUNK_PAIRS) == 1 << 26
         torch.cuda.synchronize()
     finally:
         gk.gk_destroy(ctx2)

@@ -21,7 +21,7 @@ from paper_2103_14978_amd import device, gk
 pytestmark = pytest.mark.gpu
 
 E = 2
-MAX_CALLS = 24          # more allocations than any single call makes
+MAX_CALLS = 40          # more allocations than any single call makes
 
 
 def _hook():
@@ -175,18 +175,22 @@ def test_verify(data):
 
 
 @pytest.mark.parametrize("threads", [0, 2])
-def test_filter_host(data, threads):
+@pytest.mark.parametrize("identity", [False, True], ids=["pair_read", "one-per-read"])
+@pytest.mark.parametrize("chunk", [0, 1024], ids=["one-chunk", "three-slots"])
+def test_filter_host(data, threads, identity, chunk):
     ref, ps, ra, rs = data
+    assert np.array_equal(ps.pair_read, np.arange(ps.n_pairs))
 
     def call(c):
         gk.gk_set_option(c, gk.GK_OPT_HOST_ENCODE_THREADS, threads)
+        gk.gk_set_option(c, gk.GK_OPT_HOST_CHUNK_PAIRS, chunk)
         acc = np.full(ps.n_pairs, 0xEE, np.uint8)
         est = np.full(ps.n_pairs, 0x5A5A, np.uint16)
         gk.gk_filter_host(c, ps.reads, ps.read_off, ps.cand_pos, acc, est, max_read_len=100,
-                          pair_read=ps.pair_read, e_uniform=E)
+                          pair_read=None if identity else ps.pair_read, e_uniform=E)
         assert_same(acc, est, ra, rs, "gk_filter_host after the failure was lifted")
     _each_failure(_loaded_ctx(data), call, lambda c: _filter_ok(c, data, load=False),
-                  f"gk_filter_host threads={threads}")
+                  f"gk_filter_host threads={threads} identity={identity} chunk={chunk}")
 
 
 def test_server_start(data):

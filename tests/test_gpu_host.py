@@ -187,3 +187,80 @@ def test_host_encoded_reads(gkctx, layout):
                           pair_read=ps.pair_read, e_uniform=7, packed=packed, read_len=None,
                           n_reads=len(lens))
     assert ei.value.status == gk.GK_EINVAL
+
+
+@pytest.fixture
+def small_chunks(gkctx):
+    """GK_OPT_HOST_CHUNK_PAIRS = 4096 for one test: dozens of chunks, so each
+    of the three device slots is reused many times."""
+    from paper_2103_14978_amd import gk
+    gk.gk_set_option(gkctx, gk.GK_OPT_HOST_CHUNK_PAIRS, 4096)
+    assert gk.gk_get_option(gkctx, gk.GK_OPT_HOST_CHUNK_PAIRS) == 4096
+    yield 4096
+    gk.gk_set_option(gkctx, gk.GK_OPT_HOST_CHUNK_PAIRS, 0)
+
+
+@pytest.mark.parametrize("order", ["identity", "sorted", "shuffled"])
+def test_host_chunk_ring(gkctx, small_chunks, encode_threads, order):
+    """The chunk ring: one pair per read (reads travel with their pairs,
+    slot by slot), pairs in read order (a pair chunk is filtered as soon as
+    the read chunk holding its reads is encoded) and shuffled pairs (every
+    pair chunk waits for all reads), each with a ragged last chunk.  Every
+    pair equals gk_filter on device buffers; a sample equals the oracle."""
+    from paper_2103_14978_amd import gk
+    ref = gen.c1_reference()
+    gk.gk_load_reference(gkctx, ref)
+    rng = np.random.default_rng(17)
+    if order == "identity":
+        ps = gen.c1_pairs(ref, 5, n_pairs=(60 << 12) + 333)
+        e = None
+    else:
+        ps = gen.c2_pairs(ref, 150, 7, n_pairs=(50 << 12) + 1001)
+        if order == "shuffled":
+            perm = rng.permutation(ps.n_pairs)
+        else:
+            perm = np.argsort(ps.pair_read, kind="stable")
+        ps.pair_read = ps.pair_read[perm].copy()
+        ps.cand_pos = ps.cand_pos[perm].copy()
+        e = rng.integers(0, 16, ps.n_pairs).astype(np.uint8)
+    ps.reads = ps.reads.copy()
+    ps.reads[np.arange(300, len(ps.reads), 7001)] = ord("N")
+    m = 100 if order == "identity" else 150
+    say(f"case: host chunk ring order={order} threads={encode_threads} pairs={ps.n_pairs}")
+    a, s = host_filter(gkctx, ps, max_read_len=m, e=e, e_uniform=5,
+                       identity=order == "identity", pinned=order != "sorted")
+    ee = 5 if e is None else e
+    a2, s2, _ = run_gpu(gkctx, ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, ee,
+                        max_read_len=m, load_ref=False, identity_as_null=order == "identity")
+    assert_same(a, s, a2, s2, f"host chunk ring {order} vs device buffers")
+    idx = np.sort(rng.choice(ps.n_pairs, 1 << 13, replace=False))
+    ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read[idx], ps.cand_pos[idx],
+                        ee if e is None else e[idx])
+    assert_same(a[idx], s[idx], ra, rs, f"host chunk ring {order} vs oracle")
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_host_encoded_identity_chunks(gkctx, small_chunks, layout):
+    """Host-encoded reads, one pair per read, 4096-pair chunks: the rows of
+    each chunk are staged and transposed in its slot."""
+    from paper_2103_14978_amd import gk
+    ref = gen.c1_reference()
+    gk.gk_load_reference(gkctx, ref)
+    ps = gen.c1_pairs(ref, 5, n_pairs=(40 << 12) + 19)
+    reads = ps.reads.copy()
+    reads[np.arange(500, len(reads), 7919)] = ord("N")
+    rows = (100 + 15) // 16
+    packed, lens, has_n = pack_reads_rows(reads, ps.read_off, rows, layout)
+    say(f"case: host-encoded identity chunks layout={layout} pairs={ps.n_pairs}")
+    acc = np.zeros(ps.n_pairs, np.uint8)
+    est = np.zeros(ps.n_pairs, np.uint16)
+    gk.gk_filter_host(gkctx, None, None, ps.cand_pos, acc, est, max_read_len=100,
+                      e_uniform=5, packed=packed, read_len=lens, read_has_n=has_n,
+                      packed_layout=layout, n_reads=len(lens))
+    a2, s2, _ = run_gpu(gkctx, ref, reads, ps.read_off, ps.pair_read, ps.cand_pos, 5,
+                        max_read_len=100, load_ref=False, identity_as_null=True)
+    assert_same(acc, est, a2, s2, f"host-encoded identity chunks layout={layout}")
+    assert np.any(acc == gk.GK_UNDEFINED)
+    idx = np.arange(0, ps.n_pairs, 53)
+    ra, rs = run_oracle(ref, reads, ps.read_off, ps.pair_read[idx], ps.cand_pos[idx], 5)
+    assert_same(acc[idx], est[idx], ra, rs, "host-encoded identity chunks vs oracle")
