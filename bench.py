@@ -988,7 +988,12 @@ def mixed_section(args, log, calib=None, n_pairs: int = 1 << 26) -> dict:
     tuning = [report["tile"], report["ppl"], report["sort_e"], report["blocks_per_cu"]]
     mtraffic = traffic_from_profile(mhash, n_pairs, "k_mixed_w10_config3_counters.json",
                                     tuning=tuning)
+    m_insts = traffic_from_profile(mhash, n_pairs, "k_mixed_w10_config3_counters.json",
+                                   tuning=tuning, field="valu_insts_per_launch")
     peak = valu_peak(calib)
+    # issued: the mixed kernel's VALU instructions per launch (x 64 lanes) from
+    # the committed counters, over the mean kernel time
+    m_issued = m_insts * 64 / k_m / 1e12 if m_insts else None
     out = {
         "workload": f"mixed batch, {n_pairs} pairs, read length uniform over "
                     "{64,100,150,200,250,300}, e uniform 0..floor(0.1 m) per pair, "
@@ -1006,6 +1011,8 @@ def mixed_section(args, log, calib=None, n_pairs: int = 1 << 26) -> dict:
         "roofline": {"bound": "alu", "kernel": "k_mixed<10>", "achieved": round(achieved, 3),
                      "peak": round(peak, 3), "unit": "Tops/s",
                      "frac": round(achieved / peak, 4), "traffic": mtraffic,
+                     "issued": round(m_issued, 3) if m_issued else None,
+                     "issued_frac": round(m_issued / peak, 4) if m_issued else None,
                      "traffic_GBs": (round(mtraffic / k_m / 1e9, 1) if mtraffic else None),
                      "ops_per_pair_mean": round(ops / n_pairs, 1),
                      "kernel_ms": round(k_m * 1e3, 4), "kernel_source_hash": mhash},

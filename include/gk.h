@@ -69,7 +69,9 @@ extern "C" {
 
 typedef struct gk_ctx gk_ctx;
 
-/* Create a context on HIP device `device`.  *out is set on success. */
+/* Create a context on HIP device `device`.  *out is set on success.  Tuning
+   options set in the environment (GK_<name>, see gk_set_option) apply to it;
+   GK_EINVAL for a malformed one. */
 int gk_create(int device, gk_ctx **out);
 
 /* Free the context, its resident reference and scratch.  NULL-safe. */
@@ -334,7 +336,10 @@ int gk_verify(gk_ctx *ctx, const gk_batch *batch, const uint8_t *accept, uint16_
                                             64); sets its device memory     */
 
 /* Set / get a tuning option.  GK_EINVAL for an unknown option or a value out
-   of range. */
+   of range.  gk_create also takes each option from the environment variable
+   GK_<name> of GK_OPT_<name> (GK_MIXED_TILE=8192, GK_HOST_CHUNK_PAIRS=65536,
+   ...) when it is set: a value that is not a decimal integer in the option's
+   range makes gk_create fail with GK_EINVAL, naming the variable. */
 int gk_set_option(gk_ctx *ctx, int option, int64_t value);
 int gk_get_option(const gk_ctx *ctx, int option, int64_t *value);
 

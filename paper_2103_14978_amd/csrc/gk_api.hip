@@ -1,9 +1,11 @@
 // Host side of libgk: context, resident reference, argument checks, launches.
 #include <algorithm>
 #include <atomic>
+#include <cerrno>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <mutex>
@@ -162,6 +164,47 @@ int gk_detail_fail_alloc(uint64_t nth)
     return GK_OK;
 }
 
+namespace {
+
+// Options a context takes from the environment at creation: GK_<name> for
+// option GK_OPT_<name>, a decimal integer in the option's range.
+constexpr struct {
+    const char *var;
+    int option;
+} ENV_OPTIONS[] = {
+    {"GK_PAIRS_PER_LANE", GK_OPT_PAIRS_PER_LANE},
+    {"GK_MIXED_TILE", GK_OPT_MIXED_TILE},
+    {"GK_MIXED_PAIRS_PER_LANE", GK_OPT_MIXED_PAIRS_PER_LANE},
+    {"GK_MIXED_SORT_E", GK_OPT_MIXED_SORT_E},
+    {"GK_MIXED_BLOCKS_PER_CU", GK_OPT_MIXED_BLOCKS_PER_CU},
+    {"GK_MIXED_GRAPH", GK_OPT_MIXED_GRAPH},
+    {"GK_HOST_ENCODE_THREADS", GK_OPT_HOST_ENCODE_THREADS},
+    {"GK_SERVER_PART_PAIRS", GK_OPT_SERVER_PART_PAIRS},
+    {"GK_SERVER_TICK_PAIRS", GK_OPT_SERVER_TICK_PAIRS},
+    {"GK_HOST_CHUNK_PAIRS", GK_OPT_HOST_CHUNK_PAIRS},
+};
+
+int apply_env_options(gk_ctx *ctx)
+{
+    for (const auto &o : ENV_OPTIONS) {
+        const char *v = std::getenv(o.var);
+        if (!v)
+            continue;
+        char *end = nullptr;
+        errno = 0;
+        const long long x = std::strtoll(v, &end, 10);
+        if (errno != 0 || end == v || *end != '\0')
+            return fail(ctx, GK_EINVAL,
+                        std::string("gk_create: ") + o.var + "='" + v + "' is not an integer");
+        const int st = gk_set_option(ctx, o.option, (int64_t)x);
+        if (st != GK_OK)
+            return fail(ctx, st, std::string("gk_create: ") + o.var + ": " + ctx->err);
+    }
+    return GK_OK;
+}
+
+}  // namespace
+
 int gk_create(int device, gk_ctx **out)
 {
     if (!out) {
@@ -207,6 +250,12 @@ int gk_create(int device, gk_ctx **out)
         g_create_error = std::string("gk_create: device scratch address: ") +
                          hipGetErrorName(e);
         return GK_EDEVICE;
+    }
+    const int st = apply_env_options(ctx);
+    if (st != GK_OK) {
+        g_create_error = ctx->err;
+        gk_destroy(ctx);
+        return st;
     }
     g_create_error.clear();
     *out = ctx;

@@ -209,3 +209,38 @@ def test_tiny_and_odd_references(gkctx):
             a, s, _ = run_gpu(gkctx, ref, reads, off, pr, pos, e, max_read_len=64, load_ref=False)
             ra, rs = run_oracle(ref, reads, off, pr, pos, e)
             assert_same(a, s, ra, rs, f"tiny L={L} e={e}")
+
+
+@pytest.mark.gpu
+def test_options_from_environment(monkeypatch):
+    """gk_create takes GK_<name> for each option GK_OPT_<name>; a value that is
+    not an integer in range fails the call with GK_EINVAL, naming the
+    variable, and later contexts without it are unaffected."""
+    from paper_2103_14978_amd import gk
+    monkeypatch.setenv("GK_MIXED_TILE", "8192")
+    monkeypatch.setenv("GK_HOST_CHUNK_PAIRS", "65536")
+    monkeypatch.setenv("GK_SERVER_PART_PAIRS", "4096")
+    ctx = gk.gk_create(0)
+    try:
+        assert gk.gk_get_option(ctx, gk.GK_OPT_MIXED_TILE) == 8192
+        assert gk.gk_get_option(ctx, gk.GK_OPT_HOST_CHUNK_PAIRS) == 65536
+        assert gk.gk_get_option(ctx, gk.GK_OPT_SERVER_PART_PAIRS) == 4096
+        assert gk.gk_get_option(ctx, gk.GK_OPT_MIXED_GRAPH) == 1
+    finally:
+        gk.gk_destroy(ctx)
+    for var, val in (("GK_MIXED_TILE", "3000"), ("GK_MIXED_TILE", "4k"),
+                     ("GK_HOST_ENCODE_THREADS", ""), ("GK_PAIRS_PER_LANE", "-1")):
+        monkeypatch.setenv(var, val)
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_create(0)
+        assert ei.value.status == gk.GK_EINVAL
+        assert var in str(ei.value)
+        monkeypatch.delenv(var)
+    monkeypatch.delenv("GK_HOST_CHUNK_PAIRS")
+    monkeypatch.delenv("GK_SERVER_PART_PAIRS")
+    ctx = gk.gk_create(0)
+    try:
+        assert gk.gk_get_option(ctx, gk.GK_OPT_MIXED_TILE) == 4096
+        assert gk.gk_get_option(ctx, gk.GK_OPT_HOST_CHUNK_PAIRS) == 0
+    finally:
+        gk.gk_destroy(ctx)
