@@ -21,6 +21,7 @@ HOST_SOURCES = ["gk_host_encode.cpp"]     # host-only C++ (no device code)
 ARCH = os.environ.get("GK_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_LIB = "/opt/rocm/lib"
 CXX = os.environ.get("GK_HOST_CXX", "/opt/rocm/llvm/bin/clang++")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -54,6 +55,8 @@ def build(verbose: bool = False) -> str:
         tmp = lib + ".tmp"
         cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread",
                *[objs[p] for p in parts], "-o", tmp]
+        if lib == LIB:      # trace ranges (roctx)
+            cmd += ["-L", ROCM_LIB, "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}"]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             sys.stderr.write(r.stdout + r.stderr)

@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cerrno>
+#include <cstdarg>
 #include <cmath>
 #include <cstddef>
 #include <cstdio>
@@ -14,6 +15,7 @@
 #include <string>
 
 #include "gk_internal.h"
+#include "gk_trace.h"
 #include "gk_reference.h"
 #include "gk_verify.h"
 
@@ -153,6 +155,18 @@ hipError_t gk_detail_pinned_alloc(void **p, size_t bytes)
     return hipHostMalloc(p, bytes, hipHostMallocDefault);
 }
 
+void gk_detail_log(const gk_ctx *ctx, const char *fmt, ...)
+{
+    if (!ctx || !ctx->log)
+        return;
+    char line[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(line, sizeof line, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[gk] %s\n", line);
+}
+
 extern "C" {
 
 // Test hook (not part of the public header): the nth device or pinned-host
@@ -184,6 +198,54 @@ constexpr struct {
     {"GK_HOST_CHUNK_PAIRS", GK_OPT_HOST_CHUNK_PAIRS},
 };
 
+// GK_FAULT_INJECT=alloc:N arms the allocation-failure hook once per process
+// (the N-th device or pinned allocation from the first gk_create on fails).
+std::mutex g_fault_env_mu;
+bool g_fault_env_done = false;
+
+int apply_env_flags(gk_ctx *ctx)
+{
+    if (const char *v = std::getenv("GK_LOG")) {
+        if (std::strcmp(v, "0") != 0 && std::strcmp(v, "1") != 0)
+            return fail(ctx, GK_EINVAL, std::string("gk_create: GK_LOG='") + v +
+                                            "' must be 0 or 1");
+        ctx->log = v[0] == '1';
+    }
+    if (const char *v = std::getenv("GK_AUTOTUNE")) {
+        if (!std::strcmp(v, "use"))
+            ctx->autotune = AUTOTUNE_USE;
+        else if (!std::strcmp(v, "refresh"))
+            ctx->autotune = AUTOTUNE_REFRESH;
+        else if (!std::strcmp(v, "off"))
+            ctx->autotune = AUTOTUNE_OFF;
+        else
+            return fail(ctx, GK_EINVAL, std::string("gk_create: GK_AUTOTUNE='") + v +
+                                            "' must be use, refresh or off");
+    }
+    return GK_OK;
+}
+
+// Parses GK_FAULT_INJECT before gk_create allocates anything; returns a
+// message for a malformed value, else "".
+std::string arm_fault_from_env()
+{
+    const char *v = std::getenv("GK_FAULT_INJECT");
+    if (!v)
+        return "";
+    char *end = nullptr;
+    errno = 0;
+    const unsigned long long n =
+        std::strncmp(v, "alloc:", 6) == 0 ? std::strtoull(v + 6, &end, 10) : 0ull;
+    if (n == 0 || errno != 0 || !end || *end != '\0' || v[6] == '-')
+        return std::string("gk_create: GK_FAULT_INJECT='") + v + "' must be alloc:N with N >= 1";
+    std::lock_guard<std::mutex> lk(g_fault_env_mu);
+    if (!g_fault_env_done) {
+        g_fail_alloc_at.store(n);
+        g_fault_env_done = true;
+    }
+    return "";
+}
+
 int apply_env_options(gk_ctx *ctx)
 {
     for (const auto &o : ENV_OPTIONS) {
@@ -212,6 +274,11 @@ int gk_create(int device, gk_ctx **out)
         return GK_EINVAL;
     }
     *out = nullptr;
+    const std::string fault_err = arm_fault_from_env();
+    if (!fault_err.empty()) {
+        g_create_error = fault_err;
+        return GK_EINVAL;
+    }
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
     if (e != hipSuccess || device < 0 || device >= count) {
@@ -251,7 +318,9 @@ int gk_create(int device, gk_ctx **out)
                          hipGetErrorName(e);
         return GK_EDEVICE;
     }
-    const int st = apply_env_options(ctx);
+    int st = apply_env_options(ctx);
+    if (st == GK_OK)
+        st = apply_env_flags(ctx);
     if (st != GK_OK) {
         g_create_error = ctx->err;
         gk_destroy(ctx);
@@ -305,6 +374,7 @@ const char *gk_last_error(const gk_ctx *ctx)
 
 int gk_load_reference(gk_ctx *ctx, const char *ascii, uint64_t len)
 {
+    gkd::TraceRange trace("gk_load_reference");
     if (!ctx)
         return GK_EINVAL;
     if (!ascii || len == 0)
@@ -366,6 +436,7 @@ int gk_load_reference(gk_ctx *ctx, const char *ascii, uint64_t len)
 int gk_load_reference_2bit(gk_ctx *ctx, const uint32_t *packed, uint64_t len, uint32_t layout,
                            const uint64_t *n_runs, uint64_t n_n_runs)
 {
+    gkd::TraceRange trace("gk_load_reference_2bit");
     if (!ctx)
         return GK_EINVAL;
     if (!packed || len == 0)
@@ -467,6 +538,7 @@ int gk_encode_reads(gk_ctx *ctx, const uint8_t *ascii, const uint64_t *read_off,
                     uint32_t pitch, uint32_t rows, uint32_t layout, uint32_t *packed_out,
                     uint16_t *len_out, uint8_t *has_n_out, void *stream)
 {
+    gkd::TraceRange trace("gk_encode_reads");
     if (!ctx)
         return GK_EINVAL;
     if (n_reads == 0)
@@ -635,6 +707,7 @@ extern "C" {
 
 int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
 {
+    gkd::TraceRange trace("gk_filter");
     if (!ctx)
         return GK_EINVAL;
     gkd::FilterArgs a{};
@@ -645,6 +718,10 @@ int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
     if (!g.ok)
         return fail(ctx, GK_EDEVICE, "gk_filter: hipSetDevice failed");
     const uint32_t words = (b->max_read_len + 31) / 32;
+    gk_detail_log(ctx, "gk_filter: %llu pairs, %u reads, %u words per mask, layout %u, e %s, "
+                  "pairs per lane %u (0: automatic), flags %u",
+                  (unsigned long long)b->n_pairs, b->n_reads, words, b->read_layout,
+                  b->e ? "per pair" : "uniform", ctx->pairs_per_lane, b->flags);
     hipError_t e = gkd::launch_filter(a, words, b->read_layout, ctx->pairs_per_lane,
                                       (hipStream_t)stream);
     if (e != hipSuccess)
@@ -655,6 +732,7 @@ int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
 int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *dist,
               void *stream)
 {
+    gkd::TraceRange trace("gk_verify");
     if (!ctx)
         return GK_EINVAL;
     gkd::FilterArgs a{};
@@ -710,6 +788,9 @@ int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *d
         rm = ctx->d_reads_rm;
     }
     const uint32_t words = (b->max_read_len + 31) / 32;
+    gk_detail_log(ctx, "gk_verify: %llu pairs, %s, pairs listed by %s%s",
+                  (unsigned long long)b->n_pairs, accept ? "accepted ones" : "every one",
+                  b->e ? "(length, e)" : "length", rm ? ", reads from a row-major copy" : "");
     uint32_t *groups = ctx->d_verify_list + ctx->verify_cap;
     uint32_t *deferred = groups + (ctx->verify_cap + 4095) / 4096;
     uint32_t *bins = deferred + ctx->verify_cap;
@@ -723,6 +804,7 @@ int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *d
 
 int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
 {
+    gkd::TraceRange trace("gk_filter_mixed");
     if (!ctx)
         return GK_EINVAL;
     gkd::FilterArgs a{};
@@ -744,6 +826,9 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
     // Direct launches: graphs off, variant semantics (their own kernels), or
     // a batch of more than one launch chunk (2^30 pairs).
     if (!ctx->use_graph || a.flags != 0u || b->n_pairs > (1ull << 30)) {
+        gk_detail_log(ctx, "gk_filter_mixed: %llu pairs, direct launch (tile %u, %u per lane, "
+                      "sort by e %u, %u workgroups)", (unsigned long long)b->n_pairs, x.tile,
+                      x.ppl, x.sort_e, x.blocks);
         e = gkd::launch_mixed(a, x, wmax, b->read_layout, hs);
         if (e != hipSuccess)
             return hip_fail(ctx, e, "gk_filter_mixed: launch");
@@ -759,7 +844,11 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
                                x.ppl, x.sort_e, x.blocks, x.resid_blocks, 0u};
     std::vector<uint8_t> key(sizeof shape);
     std::memcpy(key.data(), shape, sizeof shape);
-    if (!ctx->graph_exec || key != ctx->graph_key) {
+    const bool capture = !ctx->graph_exec || key != ctx->graph_key;
+    gk_detail_log(ctx, "gk_filter_mixed: %llu pairs, graph %s (words per mask up to %u, tile %u, "
+                  "%u per lane, sort by e %u, %u workgroups)", (unsigned long long)b->n_pairs,
+                  capture ? "captured" : "replayed", shape[0], x.tile, x.ppl, x.sort_e, x.blocks);
+    if (capture) {
         drop_graph(ctx);
         hipGraph_t graph = nullptr;
         e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed);
@@ -809,6 +898,7 @@ int gk_filter_mixed(gk_ctx *ctx, const gk_batch *b, void *stream)
 
 int gk_filter_mixed_noalloc(gk_ctx *ctx, const gk_batch *b, void *stream)
 {
+    gkd::TraceRange trace("gk_filter_mixed_noalloc");
     if (!ctx)
         return GK_EINVAL;
     gkd::FilterArgs a{};
@@ -943,6 +1033,7 @@ int gk_get_option(const gk_ctx *ctx, int option, int64_t *value)
 int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_pairs,
                   const char *cache_path, char *report, size_t report_cap)
 {
+    gkd::TraceRange trace("gk_tune_mixed");
     if (!ctx)
         return GK_EINVAL;
     gkd::FilterArgs a{};
@@ -982,10 +1073,28 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_
         out = std::strtol(line.c_str() + p + f.size(), nullptr, 10);
         return true;
     };
-    if (cache_path && *cache_path) {
+    auto give = [&](const char *source, const MixedConfig &c) {
+        rep << "{\"key\": \"" << key << "\", \"source\": \"" << source << "\", \"tile\": "
+            << c.tile << ", \"ppl\": " << c.ppl << ", \"sort_e\": " << c.sort_e
+            << ", \"blocks_per_cu\": " << c.blocks_per_cu << "}";
+        if (report && report_cap) {
+            std::strncpy(report, rep.str().c_str(), report_cap - 1);
+            report[report_cap - 1] = 0;
+        }
+        gk_detail_log(ctx, "gk_tune_mixed: %s, %s: tile %u, %u per lane, sort by e %u, "
+                      "%u workgroups per CU (0: full)", key.c_str(), source, c.tile, c.ppl,
+                      c.sort_e, c.blocks_per_cu);
+        return GK_OK;
+    };
+    if (ctx->autotune == AUTOTUNE_OFF)
+        return give("off", ctx->mixed);
+    if (cache_path && *cache_path && ctx->autotune == AUTOTUNE_USE) {
+        // The last valid line for the key: a refresh appends after older ones.
         std::ifstream in(cache_path);
         std::string line;
         const std::string needle = "\"key\": \"" + key + "\"";
+        bool found = false;
+        MixedConfig cached;
         while (std::getline(in, line)) {
             if (line.find(needle) == std::string::npos)
                 continue;
@@ -993,17 +1102,14 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_
             if (parse(line, "tile", t) && parse(line, "ppl", p) && parse(line, "sort_e", se) &&
                 parse(line, "blocks_per_cu", bpc) && (t == 2048 || t == 4096 || t == 8192) &&
                 (p == 1 || p == 2) && (se == 0 || se == 1) && bpc >= 0 && bpc <= 64) {
-                ctx->mixed = MixedConfig{(uint32_t)t, (uint32_t)p, (uint32_t)se, (uint32_t)bpc};
-                drop_graph(ctx);
-                rep << "{\"key\": \"" << key << "\", \"source\": \"cache\", \"tile\": " << t
-                    << ", \"ppl\": " << p << ", \"sort_e\": " << se << ", \"blocks_per_cu\": " << bpc
-                    << "}";
-                if (report && report_cap) {
-                    std::strncpy(report, rep.str().c_str(), report_cap - 1);
-                    report[report_cap - 1] = 0;
-                }
-                return GK_OK;
+                cached = MixedConfig{(uint32_t)t, (uint32_t)p, (uint32_t)se, (uint32_t)bpc};
+                found = true;
             }
+        }
+        if (found) {
+            ctx->mixed = cached;
+            drop_graph(ctx);
+            return give("cache", cached);
         }
     }
 
@@ -1087,6 +1193,9 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *b, void *stream, uint64_t sample_
         std::strncpy(report, rep.str().c_str(), report_cap - 1);
         report[report_cap - 1] = 0;
     }
+    gk_detail_log(ctx, "gk_tune_mixed: %s, measured: tile %u, %u per lane, sort by e %u, "
+                  "%u workgroups per CU (0: full), %.4f ms", key.c_str(), best.tile, best.ppl,
+                  best.sort_e, best.blocks_per_cu, best_ms);
     return GK_OK;
 }
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "gk_internal.h"
+#include "gk_trace.h"
 
 namespace {
 
@@ -145,6 +146,7 @@ void gk_detail_free_host_pipe(gk_ctx *ctx)
 
 extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
 {
+    gkd::TraceRange trace("gk_filter_host");
     if (!ctx)
         return GK_EINVAL;
     if (!b)
@@ -206,6 +208,13 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
     const uint32_t pitch =
         identity ? (uint32_t)P : (uint32_t)std::max<uint64_t>(64, (nr + 63) / 64 * 64);
 
+    gk_detail_log(ctx, "gk_filter_host: %llu pairs, %llu reads, %s, chunks of %llu pairs "
+                  "(%llu pair chunks, %llu read chunks, %u device slots), reads %s",
+                  (unsigned long long)np, (unsigned long long)nr,
+                  identity ? "one pair per read" : "pairs name their reads",
+                  (unsigned long long)P, (unsigned long long)K, (unsigned long long)Kr, S,
+                  host_encoded ? "host-encoded"
+                               : (encode_here ? "encoded on host threads" : "encoded on the GPU"));
     HostPipe &h = ctx->host;
     hipError_t e = ensure_streams(h);
     if (e != hipSuccess)
@@ -375,6 +384,7 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
             uint16_t *len_h = reinterpret_cast<uint16_t *>(st + stage_rows_bytes);
             uint8_t *has_n_h = st + stage_rows_bytes + R * sizeof(uint16_t);
             if (e == hipSuccess) {
+                gkd::TraceRange trace_enc("gk_filter_host encode rows");
                 h.pool->run([&](unsigned i, unsigned n) {
                     const uint64_t a = r0 + cnt * i / n, z = r0 + cnt * (i + 1) / n;
                     gkd::host_encode_rows(b->ascii, text_bytes, b->read_off, a, z, rows,
@@ -437,9 +447,11 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         while (e == hipSuccess && status == GK_OK && next_q < K && need_of(next_q) <= j)
             status = run_pairs(next_q++);
     }
+    gkd::trace_push("gk_filter_host drain");
     const hipError_t e1 = hipStreamSynchronize(h.s_in);
     const hipError_t e2 = hipStreamSynchronize(h.s_comp);
     const hipError_t e3 = hipStreamSynchronize(h.s_out);
+    gkd::trace_pop();
     if (status != GK_OK)
         return status;
     if (e == hipSuccess)

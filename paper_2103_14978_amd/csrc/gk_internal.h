@@ -83,6 +83,8 @@ struct gk_ctx {
     uint32_t use_graph = 1;                   // GK_OPT_MIXED_GRAPH
     uint32_t host_encode_threads = 0;         // GK_OPT_HOST_ENCODE_THREADS
     uint64_t host_chunk_pairs = 0;            // GK_OPT_HOST_CHUNK_PAIRS (0: automatic)
+    uint32_t log = 0;                         // GK_LOG: one stderr line per decision
+    uint32_t autotune = 0;                    // GK_AUTOTUNE: AUTOTUNE_USE / _REFRESH / _OFF
     uint64_t server_part_pairs = 1u << 17;    // GK_OPT_SERVER_PART_PAIRS
     uint64_t server_tick_pairs = 1u << 20;    // GK_OPT_SERVER_TICK_PAIRS
     uint32_t *d_mixed_counters = nullptr;     // [tile counter, residual count]
@@ -110,6 +112,16 @@ struct gk_ctx {
     uint32_t *d_reads_rm = nullptr;           // gk_verify: row-major copy of the reads
     uint64_t reads_rm_cap = 0;                // (words)
 };
+
+// gk_tune_mixed's use of its cache (environment GK_AUTOTUNE=use|refresh|off):
+// take a cached choice or measure and append (use), measure and append
+// whatever the cache holds (refresh), or keep the context's tuning and time
+// nothing (off).
+constexpr uint32_t AUTOTUNE_USE = 0, AUTOTUNE_REFRESH = 1, AUTOTUNE_OFF = 2;
+
+// One line "[gk] ..." on stderr when the context was created with GK_LOG=1:
+// the choices a call makes (kernel, chunking, graph capture or replay, tuning).
+void gk_detail_log(const gk_ctx *ctx, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 
 // Releases the buffers, streams and events of gk_filter_host.
 void gk_detail_free_host_pipe(gk_ctx *ctx);

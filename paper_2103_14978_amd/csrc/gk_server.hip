@@ -37,6 +37,7 @@
 #include <vector>
 
 #include "gk_internal.h"
+#include "gk_trace.h"
 
 namespace {
 
@@ -404,6 +405,7 @@ void loader_main(gk_server *s)
         hipStream_t st = s->s_copy;
         if (s->mode == GK_SERVER_BATCHED && (s->admitted++ & 1u))
             st = s->s_copy2;
+        gkd::trace_push("gk_server load");
         hipError_t e = load_request(s, q, st);
         if (e == hipSuccess && inject)
             e = hipErrorInvalidValue;
@@ -418,6 +420,7 @@ void loader_main(gk_server *s)
             const hipError_t es = hipStreamSynchronize(s->s_copy);   // always drained
             if (e == hipSuccess)
                 e = es;
+            gkd::trace_pop();
             lk.lock();
             if (e != hipSuccess) {
                 finish(s, q, GK_EDEVICE);
@@ -430,6 +433,7 @@ void loader_main(gk_server *s)
         }
         if (e == hipSuccess)
             e = hipEventRecord(q->ready, st);
+        gkd::trace_pop();
         lk.lock();
         if (e != hipSuccess || s->stopping) {
             // A failure here, or in another thread while this request was
@@ -484,6 +488,7 @@ void scheduler_main(gk_server *s)
         s->tick_buf ^= 1;
         lk.unlock();
 
+        gkd::trace_push("gk_server tick");
         gkd::BatchTable *h = s->h_table[t.buf];
         h->n_batches = (uint32_t)t.parts.size();
         uint32_t tiles = 0;
@@ -503,6 +508,7 @@ void scheduler_main(gk_server *s)
             e = hipGraphLaunch(s->graph[t.buf], s->s_compute);
         if (e == hipSuccess)
             e = hipEventRecord(s->tick_done[t.buf], s->s_compute);
+        gkd::trace_pop();
         lk.lock();
         if (e != hipSuccess || s->stopping) {
             // A failure here, or in another thread meanwhile (the completer
@@ -540,6 +546,7 @@ void completer_main(gk_server *s)
         s->completing = true;
         const bool inject = s->fail_tick_at != 0 && ++s->ticks_taken == s->fail_tick_at;
         lk.unlock();
+        gkd::trace_push("gk_server complete");
         hipError_t e = hipEventSynchronize(s->tick_done[t.buf]);
         const int64_t t_kernel_done = now_us();
         const bool released = e == hipSuccess;
@@ -561,6 +568,7 @@ void completer_main(gk_server *s)
         if (e == hipSuccess && inject)
             e = hipErrorInvalidValue;
         const int64_t t_copied = now_us();
+        gkd::trace_pop();
         lk.lock();
         if (e == hipSuccess && s->tick_log.size() < TICK_LOG_CAP)
             s->tick_log.push_back(gk_tick_record{t.t_launch, t_kernel_done, t_copied,
@@ -719,6 +727,12 @@ int gk_server_start(gk_ctx *ctx, uint64_t device_budget_bytes, uint32_t max_slot
         return gk_detail_fail(ctx, code,
                               std::string("gk_server_start: ") + hipGetErrorName(e));
     }
+    gk_detail_log(ctx, "gk_server_start: %s, %llu device bytes, %u slots, words per mask up "
+                  "to %u; ticks of up to %llu pairs, parts of up to %llu, tile %u",
+                  mode == GK_SERVER_BATCHED ? "batched" : "sequential",
+                  (unsigned long long)device_budget_bytes, max_slots, s->wmax,
+                  (unsigned long long)s->tick_pairs, (unsigned long long)s->part_pairs,
+                  s->margs.tile);
     s->loader = std::thread(loader_main, s);
     if (mode == GK_SERVER_BATCHED) {
         s->scheduler = std::thread(scheduler_main, s);

@@ -300,7 +300,9 @@ int main()
     {
         Batch b = make_batch(rng, 5, 64);
         make_pairs(rng, b, Order::Identity, 0, false);
+        ctx.log = 1;            // one log line through the stand-in's logger
         run(&ctx, b, Mode{}, "five reads, one pair each");
+        ctx.log = 0;
         Batch z = make_batch(rng, 0, 64);
         make_pairs(rng, z, Order::Sorted, 300, true);
         Mode md;

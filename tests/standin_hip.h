@@ -12,7 +12,9 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdarg>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
@@ -335,4 +337,18 @@ hipError_t gk_detail_pinned_alloc(void **p, size_t bytes)
 {
     *p = zalloc(bytes);
     return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+// The library's log line (defined with the entry points, which a check
+// program does not build).
+void gk_detail_log(const gk_ctx *ctx, const char *fmt, ...)
+{
+    if (!ctx || !ctx->log)
+        return;
+    va_list ap;
+    va_start(ap, fmt);
+    std::fputs("[gk] ", stderr);
+    std::vfprintf(stderr, fmt, ap);
+    std::fputs("\n", stderr);
+    va_end(ap);
 }

@@ -244,3 +244,23 @@ def test_options_from_environment(monkeypatch):
         assert gk.gk_get_option(ctx, gk.GK_OPT_HOST_CHUNK_PAIRS) == 0
     finally:
         gk.gk_destroy(ctx)
+
+
+@pytest.mark.gpu
+def test_fault_injection_from_environment(monkeypatch):
+    """GK_FAULT_INJECT=alloc:N arms the allocation failure once per process:
+    with N = 1 the first gk_create's own allocation fails (GK_ENOMEM) and the
+    next gk_create works; a malformed value fails gk_create with GK_EINVAL."""
+    from paper_2103_14978_amd import gk
+    for val in ("alloc:0", "alloc:-3", "alloc", "memory:2", "alloc:2x"):
+        monkeypatch.setenv("GK_FAULT_INJECT", val)
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_create(0)
+        assert ei.value.status == gk.GK_EINVAL and "GK_FAULT_INJECT" in str(ei.value)
+    monkeypatch.setenv("GK_FAULT_INJECT", "alloc:1")
+    with pytest.raises(gk.GkError) as ei:
+        gk.gk_create(0)
+    assert ei.value.status == gk.GK_ENOMEM
+    ctx = gk.gk_create(0)           # armed once: this one allocates normally
+    gk.gk_destroy(ctx)
+    monkeypatch.delenv("GK_FAULT_INJECT")

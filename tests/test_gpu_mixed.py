@@ -176,3 +176,94 @@ def test_tuner_report_and_cache(gkctx, c3, tmp_path):
     for opt, val in ((gk.GK_OPT_MIXED_TILE, 4096), (gk.GK_OPT_MIXED_PAIRS_PER_LANE, 1),
                      (gk.GK_OPT_MIXED_SORT_E, 1), (gk.GK_OPT_MIXED_BLOCKS_PER_CU, 0)):
         gk.gk_set_option(gkctx, opt, val)
+
+
+def test_tuner_environment_modes(c3, tmp_path, monkeypatch, capfd):
+    """Contexts created with GK_AUTOTUNE: off keeps the context's tuning and
+    times nothing; refresh measures whatever the cache holds and appends, and
+    a later context with use takes the last line for the key.  GK_LOG=1
+    prints each choice.  Results after each equal the oracle."""
+    import torch
+    from paper_2103_14978_amd import device
+    ref, ps, ra, rs = c3
+    cache = tmp_path / "tune.jsonl"
+
+    def context(mode, tile=None):
+        monkeypatch.setenv("GK_AUTOTUNE", mode)
+        monkeypatch.setenv("GK_LOG", "1")
+        if tile:
+            monkeypatch.setenv("GK_MIXED_TILE", str(tile))
+        else:
+            monkeypatch.delenv("GK_MIXED_TILE", raising=False)
+        c = gk.gk_create(0)
+        gk.gk_load_reference(c, ref)
+        return c
+
+    def tune_and_check(c, label):
+        dr = device.encode_reads(c, ps.reads, ps.read_off, max_len=300)
+        dp = device.upload_pairs(ps.pair_read, ps.cand_pos, ps.e)
+        b = device.batch_for(dr, dp, max_read_len=300)
+        rep = json.loads(gk.gk_tune_mixed(c, b, None, sample_pairs=1 << 14,
+                                          cache_path=str(cache)))
+        gk.gk_filter_mixed(c, b, None)
+        torch.cuda.synchronize()
+        a, s = device.results(dp)
+        assert_same(a, s, ra, rs, label)
+        return rep
+
+    say("case: tuner GK_AUTOTUNE=off")
+    c = context("off", tile=8192)
+    try:
+        rep = tune_and_check(c, "autotune off")
+        assert rep["source"] == "off" and rep["tile"] == 8192
+        assert gk.gk_get_option(c, gk.GK_OPT_MIXED_TILE) == 8192
+    finally:
+        gk.gk_destroy(c)
+    assert not cache.exists()
+    err = capfd.readouterr().err
+    assert "[gk] gk_tune_mixed:" in err and "off: tile 8192" in err
+    assert "[gk] gk_filter_mixed:" in err and "graph captured" in err
+
+    say("case: tuner GK_AUTOTUNE=refresh over a planted cache line")
+    c = context("use")
+    try:
+        first = tune_and_check(c, "autotune use, measured")
+        assert first["source"] == "measured"
+    finally:
+        gk.gk_destroy(c)
+    # a planted line for the same key, with a tuning the tuner never picks
+    # by itself on this sample only by chance: use takes it, refresh ignores it
+    planted = {"key": first["key"], "tile": 2048, "ppl": 2, "sort_e": 0,
+               "blocks_per_cu": 1, "ms": 0.0}
+    with open(cache, "a") as f:
+        f.write(json.dumps(planted) + "\n")
+    c = context("use")
+    try:
+        rep = tune_and_check(c, "autotune use, planted line")
+        assert rep["source"] == "cache"
+        assert (rep["tile"], rep["ppl"], rep["sort_e"], rep["blocks_per_cu"]) == (2048, 2, 0, 1)
+    finally:
+        gk.gk_destroy(c)
+    c = context("refresh")
+    try:
+        rep = tune_and_check(c, "autotune refresh")
+        assert rep["source"] == "measured"
+        refreshed = (rep["tile"], rep["ppl"], rep["sort_e"], rep["blocks_per_cu"])
+    finally:
+        gk.gk_destroy(c)
+    assert len(cache.read_text().splitlines()) == 3
+    c = context("use")
+    try:
+        rep = tune_and_check(c, "autotune use after refresh")
+        assert rep["source"] == "cache"
+        assert (rep["tile"], rep["ppl"], rep["sort_e"], rep["blocks_per_cu"]) == refreshed
+    finally:
+        gk.gk_destroy(c)
+    err = capfd.readouterr().err
+    assert "measured: tile" in err and "cache: tile" in err
+    for var, val in (("GK_AUTOTUNE", "sometimes"), ("GK_LOG", "yes")):
+        monkeypatch.setenv(var, val)
+        with pytest.raises(gk.GkError) as ei:
+            gk.gk_create(0)
+        assert ei.value.status == gk.GK_EINVAL and var in str(ei.value)
+        monkeypatch.delenv(var)

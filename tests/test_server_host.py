@@ -17,6 +17,7 @@ CSRC = os.path.join(ROOT, "paper_2103_14978_amd", "csrc")
 # waiting thread as still holding its mutex
 CXX = "/opt/rocm/llvm/bin/clang++" if os.path.exists("/opt/rocm/llvm/bin/clang++") else None
 ROCM_INCLUDE = "/opt/rocm/include"
+ROCM_LIB = "/opt/rocm/lib"        # trace ranges (roctx)
 
 
 @pytest.mark.skipif(CXX is None or not os.path.isdir(ROCM_INCLUDE),
@@ -28,7 +29,8 @@ def test_server_host_logic(tmp_path, sanitize):
            "-I", ROCM_INCLUDE, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-x", "c++", os.path.join(CSRC, "gk_server.hip"),
            "-x", "c++", os.path.join(HERE, "server_check.cpp"),
-           os.path.join(CSRC, "gk_host_encode.cpp"), "-o", str(exe)]
+           os.path.join(CSRC, "gk_host_encode.cpp"), "-L", ROCM_LIB,
+           "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{ROCM_LIB}", "-o", str(exe)]
     if sanitize:
         cmd[5:5] = [f"-fsanitize={sanitize}", "-fno-sanitize-recover=all"]
     r = subprocess.run(cmd, capture_output=True, text=True)
