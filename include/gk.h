@@ -398,13 +398,16 @@ int gk_filter_mixed_noalloc(gk_ctx *ctx, const gk_batch *batch, void *stream);
  * 4096 / 8192, 1 or 2 pairs per lane, sort by e or not, full or half
  * persistent grid) on the first sample_pairs pairs of the batch (0 = all),
  * median of 5 runs each after a warm-up, and keeps the fastest in the
- * context.  The outputs of the sampled pairs are written (correct results:
- * every tuning gives the same ones).  Synchronous.
+ * context.  When it times candidates, the outputs of the sampled pairs are
+ * written (correct results: every tuning gives the same ones).  Synchronous.
  *
  * cache_path (HOST string or NULL): a text file of JSON lines keyed by
  * device architecture, CU count, words per mask, read layout, threshold mode
- * and batch size (power-of-two bucket).  A matching line is used without
- * timing anything; otherwise the measured choice is appended.
+ * and batch size (power-of-two bucket).  The last matching line is used
+ * without timing anything; otherwise the measured choice is appended.  A
+ * context created with GK_AUTOTUNE=refresh in the environment measures and
+ * appends whatever the cache holds; with GK_AUTOTUNE=off it keeps its
+ * current tuning, times nothing and reports source "off".
  * report (HOST, report_cap bytes, or NULL): a JSON description of the
  * choice and of every candidate's time, NUL-terminated, truncated to fit.
  */

@@ -9,7 +9,7 @@
 // (Sec. 3.5).
 #include <algorithm>
 #include <string>
-#include <vector>
+#include <cstdint>
 
 #include "gk_internal.h"
 #include "gk_trace.h"
@@ -280,24 +280,24 @@ extern "C" int gk_filter_host(gk_ctx *ctx, const gk_host_batch *b)
         }
     }
 
-    // Last read chunk pair chunk q needs (found when q is first considered).
-    std::vector<int64_t> need(K, -1);
+    // Last read chunk pair chunk q needs.  Pair chunks are considered in
+    // order, so only the next one's is kept (found when it is first asked).
+    uint64_t need_q = UINT64_MAX, need_val = 0;
     auto need_of = [&](uint64_t q) -> uint64_t {
-        if (need[q] < 0) {
-            if (identity) {
-                need[q] = (int64_t)q;
-            } else {
-                const uint64_t q0 = q * P, q1 = std::min(np, q0 + P);
-                uint32_t mx = 0;
-                for (uint64_t i = q0; i < q1; ++i) {
-                    const uint32_t r = b->pair_read[i];
-                    if (r < nr && r > mx)
-                        mx = r;          // pairs of reads >= n_reads are GK_INVALID
-                }
-                need[q] = (int64_t)std::min<uint64_t>(Kr - 1, nr ? mx / R : 0);
+        if (identity)
+            return q;
+        if (need_q != q) {
+            const uint64_t q0 = q * P, q1 = std::min(np, q0 + P);
+            uint32_t mx = 0;
+            for (uint64_t i = q0; i < q1; ++i) {
+                const uint32_t r = b->pair_read[i];
+                if (r < nr && r > mx)
+                    mx = r;          // pairs of reads >= n_reads are GK_INVALID
             }
+            need_q = q;
+            need_val = std::min<uint64_t>(Kr - 1, nr ? mx / R : 0);
         }
-        return (uint64_t)need[q];
+        return need_val;
     };
 
     // Pair chunk q: copies in, filter, copies out, in slot q % S.  Returns a
