@@ -273,6 +273,8 @@ def main() -> int:
     ap.add_argument("--ref-len", type=int, default=3_100_000_000,
                     help="served: reference length")
     ap.add_argument("--slo-ms", type=float, default=25.0, help="served: p99 target")
+    ap.add_argument("--served-modes", default="served,per_request",
+                    help="served: which servers to run (served = batched, per_request)")
     ap.add_argument("--pageable", action="store_true",
                     help="served: keep requests in pageable host memory (default: pinned)")
     ap.add_argument("--tune-sample", type=int, default=1 << 26,
@@ -1244,9 +1246,11 @@ def served_section(args, log, pool_size: int, lambdas, duration: float,
                         "copy_out_max_ms": round(float((w[:, 2] - w[:, 1]).max() / 1e3), 3)}
         return rec
 
-    results = {}
-    for mode_name, mode in (("served", gk.GK_SERVER_BATCHED),
-                            ("per_request", gk.GK_SERVER_SEQUENTIAL)):
+    results = {"served": [], "per_request": []}
+    modes = [m for m in (("served", gk.GK_SERVER_BATCHED),
+                         ("per_request", gk.GK_SERVER_SEQUENTIAL))
+             if m[0] in getattr(args, "served_modes", "served,per_request").split(",")]
+    for mode_name, mode in modes:
         results[mode_name] = []
         saturated = False
         # An untimed first round at a moderate rate warms the server's first

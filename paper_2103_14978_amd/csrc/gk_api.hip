@@ -196,6 +196,7 @@ constexpr struct {
     {"GK_SERVER_PART_PAIRS", GK_OPT_SERVER_PART_PAIRS},
     {"GK_SERVER_TICK_PAIRS", GK_OPT_SERVER_TICK_PAIRS},
     {"GK_HOST_CHUNK_PAIRS", GK_OPT_HOST_CHUNK_PAIRS},
+    {"GK_SERVER_COPY_STREAMS", GK_OPT_SERVER_COPY_STREAMS},
 };
 
 // GK_FAULT_INJECT=alloc:N arms the allocation-failure hook once per process
@@ -980,6 +981,11 @@ int gk_set_option(gk_ctx *ctx, int option, int64_t value)
             return fail(ctx, GK_EINVAL, "gk_set_option: server tick pairs must be 4096..2^26");
         ctx->server_tick_pairs = (uint64_t)value;
         return GK_OK;
+    case GK_OPT_SERVER_COPY_STREAMS:
+        if (value < 1 || value > 4)
+            return fail(ctx, GK_EINVAL, "gk_set_option: server copy streams must be 1..4");
+        ctx->server_copy_streams = (uint32_t)value;
+        return GK_OK;
     case GK_OPT_HOST_CHUNK_PAIRS:
         if (value != 0 && (value < 64 || value > (1ll << 26)))
             return fail(ctx, GK_EINVAL, "gk_set_option: host chunk pairs must be 0 or 64..2^26");
@@ -1024,6 +1030,9 @@ int gk_get_option(const gk_ctx *ctx, int option, int64_t *value)
         return GK_OK;
     case GK_OPT_HOST_CHUNK_PAIRS:
         *value = (int64_t)ctx->host_chunk_pairs;
+        return GK_OK;
+    case GK_OPT_SERVER_COPY_STREAMS:
+        *value = ctx->server_copy_streams;
         return GK_OK;
     default:
         return GK_EINVAL;

@@ -87,6 +87,7 @@ struct gk_ctx {
     uint32_t autotune = 0;                    // GK_AUTOTUNE: AUTOTUNE_USE / _REFRESH / _OFF
     uint64_t server_part_pairs = 1u << 17;    // GK_OPT_SERVER_PART_PAIRS
     uint64_t server_tick_pairs = 1u << 20;    // GK_OPT_SERVER_TICK_PAIRS
+    uint32_t server_copy_streams = 4;         // GK_OPT_SERVER_COPY_STREAMS
     uint32_t *d_mixed_counters = nullptr;     // [tile counter, residual count]
     uint32_t *d_resid = nullptr;              // residual pair list
     uint64_t resid_cap = 0;

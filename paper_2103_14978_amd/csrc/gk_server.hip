@@ -145,8 +145,13 @@ struct gk_server {
     uint64_t budget = 0;
     Arena arena;
     uint8_t *d_arena = nullptr;
-    hipStream_t s_copy = nullptr, s_compute = nullptr, s_d2h = nullptr;
-    hipStream_t s_copy2 = nullptr;         // batched mode: every other request
+    // Copy streams: the loader takes them in turn in batched mode, so one
+    // request's transfers and encoding overlap the next ones'; sequential
+    // mode uses the first alone.
+    static constexpr uint32_t MAX_COPY_STREAMS = 4;
+    hipStream_t s_copy[MAX_COPY_STREAMS] = {};
+    uint32_t n_copy = 1;
+    hipStream_t s_compute = nullptr, s_d2h = nullptr;
     uint64_t admitted = 0;                 // requests admitted so far
     std::mutex mu;
     std::condition_variable cv;
@@ -342,9 +347,9 @@ void fail_all(gk_server *s, const std::string &msg)
     // and the tick the completer is copying out stays with the completer.
     // The loader and the scheduler finish the requests they hold themselves.
     s->err = msg;
-    (void)hipStreamSynchronize(s->s_copy);
-    if (s->s_copy2)
-        (void)hipStreamSynchronize(s->s_copy2);
+    for (hipStream_t st : s->s_copy)
+        if (st)
+            (void)hipStreamSynchronize(st);
     // Requests with a part in the tick being completed end when the
     // completer hands that part back.
     for (auto *q : s->pending)
@@ -400,11 +405,9 @@ void loader_main(gk_server *s)
         const bool inject = s->fail_load_at != 0 && ++s->loads == s->fail_load_at;
         lk.unlock();
 
-        // Batched mode alternates two copy streams, so one request's
-        // transfers and encoding overlap the next one's.
-        hipStream_t st = s->s_copy;
-        if (s->mode == GK_SERVER_BATCHED && (s->admitted++ & 1u))
-            st = s->s_copy2;
+        // Batched mode takes the copy streams in turn.
+        const hipStream_t st =
+            s->s_copy[s->mode == GK_SERVER_BATCHED ? s->admitted++ % s->n_copy : 0];
         gkd::trace_push("gk_server load");
         hipError_t e = load_request(s, q, st);
         if (e == hipSuccess && inject)
@@ -413,11 +416,11 @@ void loader_main(gk_server *s)
             // One request at a time on one stream: copy in, encode, filter, copy out.
             if (e == hipSuccess) {
                 const gkd::FilterArgs a = args_for(s, q, 0, q->r.n_pairs);
-                e = gkd::launch_filter(a, s->wmax, GK_READS_SPLIT, 0, s->s_copy);
+                e = gkd::launch_filter(a, s->wmax, GK_READS_SPLIT, 0, st);
             }
             if (e == hipSuccess)
-                e = copy_out(q, 0, q->r.n_pairs, s->s_copy);
-            const hipError_t es = hipStreamSynchronize(s->s_copy);   // always drained
+                e = copy_out(q, 0, q->r.n_pairs, st);
+            const hipError_t es = hipStreamSynchronize(st);   // always drained
             if (e == hipSuccess)
                 e = es;
             gkd::trace_pop();
@@ -592,7 +595,10 @@ void destroy_server(gk_server *s)
     DeviceScope dev(s->ctx->device);
     // After a failure, ticks launched before it may still run: nothing the
     // server's streams use is freed before they are drained.
-    for (hipStream_t st : {s->s_copy, s->s_copy2, s->s_compute, s->s_d2h})
+    for (hipStream_t st : s->s_copy)
+        if (st)
+            (void)hipStreamSynchronize(st);
+    for (hipStream_t st : {s->s_compute, s->s_d2h})
         if (st)
             (void)hipStreamSynchronize(st);
     for (int k = 0; k < 2; ++k) {
@@ -616,7 +622,10 @@ void destroy_server(gk_server *s)
         (void)hipFree(s->d_counters);
     if (s->d_resid)
         (void)hipFree(s->d_resid);
-    for (hipStream_t st : {s->s_copy, s->s_copy2, s->s_compute, s->s_d2h})
+    for (hipStream_t st : s->s_copy)
+        if (st)
+            (void)hipStreamDestroy(st);
+    for (hipStream_t st : {s->s_compute, s->s_d2h})
         if (st)
             (void)hipStreamDestroy(st);
     delete s;
@@ -654,7 +663,10 @@ int gk_server_start(gk_ctx *ctx, uint64_t device_budget_bytes, uint32_t max_slot
     s->budget = device_budget_bytes;
     s->arena.init(device_budget_bytes);
     hipError_t e = gk_dmalloc(&s->d_arena, device_budget_bytes);
-    for (hipStream_t *st : {&s->s_copy, &s->s_copy2, &s->s_compute, &s->s_d2h})
+    s->n_copy = mode == GK_SERVER_BATCHED ? ctx->server_copy_streams : 1u;
+    for (uint32_t k = 0; k < s->n_copy && e == hipSuccess; ++k)
+        e = hipStreamCreateWithFlags(&s->s_copy[k], hipStreamNonBlocking);
+    for (hipStream_t *st : {&s->s_compute, &s->s_d2h})
         if (e == hipSuccess)
             e = hipStreamCreateWithFlags(st, hipStreamNonBlocking);
     if (e == hipSuccess)
@@ -728,9 +740,9 @@ int gk_server_start(gk_ctx *ctx, uint64_t device_budget_bytes, uint32_t max_slot
                               std::string("gk_server_start: ") + hipGetErrorName(e));
     }
     gk_detail_log(ctx, "gk_server_start: %s, %llu device bytes, %u slots, words per mask up "
-                  "to %u; ticks of up to %llu pairs, parts of up to %llu, tile %u",
-                  mode == GK_SERVER_BATCHED ? "batched" : "sequential",
-                  (unsigned long long)device_budget_bytes, max_slots, s->wmax,
+                  "to %u, %u copy streams; ticks of up to %llu pairs, parts of up to %llu, "
+                  "tile %u", mode == GK_SERVER_BATCHED ? "batched" : "sequential",
+                  (unsigned long long)device_budget_bytes, max_slots, s->wmax, s->n_copy,
                   (unsigned long long)s->tick_pairs, (unsigned long long)s->part_pairs,
                   s->margs.tile);
     s->loader = std::thread(loader_main, s);

@@ -37,6 +37,7 @@ GK_OPT_HOST_ENCODE_THREADS = 7
 GK_OPT_SERVER_PART_PAIRS = 8
 GK_OPT_SERVER_TICK_PAIRS = 9
 GK_OPT_HOST_CHUNK_PAIRS = 10
+GK_OPT_SERVER_COPY_STREAMS = 11
 STATUS_NAMES = {0: "GK_OK", -1: "GK_EINVAL", -2: "GK_ENOMEM", -3: "GK_EDEVICE",
                 -4: "GK_ENOREF", -5: "GK_ERANGE", -7: "GK_ETIMEOUT", -8: "GK_ECANCELED"}
 

@@ -348,6 +348,17 @@ int main()
     for (auto &q : reqs)
         total += q.pos.size();
     CHECK(ticks >= total / 4096, "split run took only %llu ticks", (unsigned long long)ticks);
+    // The loader's copy streams taken in turn: two, and one, with random
+    // delays before every stream operation.
+    g_jitter_us = 20;
+    ctx.server_copy_streams = 2;
+    run_batch(&ctx, GK_SERVER_BATCHED, reqs, identity, 4, 1ull << 28, 64,
+              "batched split, 2 copy streams, delays");
+    ctx.server_copy_streams = 1;
+    run_batch(&ctx, GK_SERVER_BATCHED, reqs, identity, 4, 1ull << 28, 64,
+              "batched split, 1 copy stream, delays");
+    ctx.server_copy_streams = 4;
+    g_jitter_us = 0;
     ctx.mixed.tile = 8192;
     ctx.server_part_pairs = 3000;
     ctx.server_tick_pairs = 10000;

@@ -97,7 +97,9 @@ def test_errors(gkctx):
                          (gk.GK_OPT_HOST_ENCODE_THREADS, -1),
                          (gk.GK_OPT_HOST_ENCODE_THREADS, 65),
                          (gk.GK_OPT_HOST_CHUNK_PAIRS, 63),
-                         (gk.GK_OPT_HOST_CHUNK_PAIRS, (1 << 26) + 1), (999, 0)):
+                         (gk.GK_OPT_HOST_CHUNK_PAIRS, (1 << 26) + 1),
+                         (gk.GK_OPT_SERVER_COPY_STREAMS, 0),
+                         (gk.GK_OPT_SERVER_COPY_STREAMS, 5), (999, 0)):
             with pytest.raises(gk.GkError) as ei:
                 gk.gk_set_option(ctx2, opt, val)
             assert ei.value.status == gk.GK_EINVAL
@@ -109,6 +111,9 @@ def test_errors(gkctx):
         assert gk.gk_get_option(ctx2, gk.GK_OPT_HOST_CHUNK_PAIRS) == 0
         gk.gk_set_option(ctx2, gk.GK_OPT_HOST_CHUNK_PAIRS, 1 << 26)
         assert gk.gk_get_option(ctx2, gk.GK_OPT_HOST_CHUNK_PAIRS) == 1 << 26
+        assert gk.gk_get_option(ctx2, gk.GK_OPT_SERVER_COPY_STREAMS) == 4
+        gk.gk_set_option(ctx2, gk.GK_OPT_SERVER_COPY_STREAMS, 1)
+        assert gk.gk_get_option(ctx2, gk.GK_OPT_SERVER_COPY_STREAMS) == 1
         torch.cuda.synchronize()
     finally:
         gk.gk_destroy(ctx2)

@@ -98,7 +98,8 @@ def test_tiny_budget_and_slots_queue(gkctx, served):
 
 SERVER_DEFAULTS = {gk.GK_OPT_SERVER_PART_PAIRS: 1 << 17, gk.GK_OPT_SERVER_TICK_PAIRS: 1 << 20,
                    gk.GK_OPT_MIXED_TILE: 4096, gk.GK_OPT_MIXED_PAIRS_PER_LANE: 1,
-                   gk.GK_OPT_MIXED_SORT_E: 1, gk.GK_OPT_MIXED_BLOCKS_PER_CU: 0}
+                   gk.GK_OPT_MIXED_SORT_E: 1, gk.GK_OPT_MIXED_BLOCKS_PER_CU: 0,
+                   gk.GK_OPT_SERVER_COPY_STREAMS: 4}
 
 
 def with_options(ctx, opts, fn):
@@ -128,6 +129,22 @@ def test_requests_split_over_ticks(gkctx, served, part, tick, tile, ppl):
     assert ticks >= total // tick
     for k, ((a, s), (ra, rs)) in enumerate(zip(outs, want)):
         assert_same(a, s, ra, rs, f"split request {k}")
+
+
+@pytest.mark.parametrize("streams", [1, 2, 3])
+def test_copy_streams(gkctx, served, streams):
+    """The loader taking 1, 2 or 3 copy streams in turn (4 is the default),
+    with requests split over ticks: every request's bytes equal the
+    oracle's."""
+    ref, reqs, want = served
+    gk.gk_load_reference(gkctx, ref)
+    say(f"case: serve copy streams={streams}")
+    opts = {gk.GK_OPT_SERVER_COPY_STREAMS: streams, gk.GK_OPT_SERVER_PART_PAIRS: 3000,
+            gk.GK_OPT_SERVER_TICK_PAIRS: 20_000}
+    outs, (ticks, max_parts, pairs) = with_options(gkctx, opts, lambda: run_server(gkctx, reqs))
+    assert pairs == sum(ps.n_pairs for ps, _ in reqs)
+    for k, ((a, s), (ra, rs)) in enumerate(zip(outs, want)):
+        assert_same(a, s, ra, rs, f"copy streams {streams} request {k}")
 
 
 def test_split_requests_one_candidate_per_read(gkctx, served):
