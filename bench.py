@@ -240,7 +240,7 @@ def main() -> int:
                     help="plain: skip the served section (config 4)")
     ap.add_argument("--served-pool", type=int, default=256,
                     help="plain: pool requests of the served section")
-    ap.add_argument("--served-lambdas", default="2000,3000,4000,5000,6000",
+    ap.add_argument("--served-lambdas", default="3000,4000,5000,6000,7000",
                     help="plain: arrival rates of the served section")
     ap.add_argument("--served-duration", type=float, default=5.0,
                     help="plain: seconds of arrivals per rate of the served section")
