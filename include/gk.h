@@ -337,7 +337,7 @@ int gk_verify(gk_ctx *ctx, const gk_batch *batch, const uint8_t *accept, uint16_
 #define GK_OPT_SERVER_COPY_STREAMS 11  /* gk_server_start, batched mode:
                                             streams the loader takes in turn
                                             for requests' copies in and
-                                            encoding, 1..4 (default 4)      */
+                                            encoding, 1..8 (default 4)      */
 
 /* Set / get a tuning option.  GK_EINVAL for an unknown option or a value out
    of range.  gk_create also takes each option from the environment variable

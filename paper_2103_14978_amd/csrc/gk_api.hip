@@ -982,8 +982,8 @@ int gk_set_option(gk_ctx *ctx, int option, int64_t value)
         ctx->server_tick_pairs = (uint64_t)value;
         return GK_OK;
     case GK_OPT_SERVER_COPY_STREAMS:
-        if (value < 1 || value > 4)
-            return fail(ctx, GK_EINVAL, "gk_set_option: server copy streams must be 1..4");
+        if (value < 1 || value > 8)
+            return fail(ctx, GK_EINVAL, "gk_set_option: server copy streams must be 1..8");
         ctx->server_copy_streams = (uint32_t)value;
         return GK_OK;
     case GK_OPT_HOST_CHUNK_PAIRS:

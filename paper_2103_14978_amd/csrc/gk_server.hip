@@ -148,7 +148,7 @@ struct gk_server {
     // Copy streams: the loader takes them in turn in batched mode, so one
     // request's transfers and encoding overlap the next ones'; sequential
     // mode uses the first alone.
-    static constexpr uint32_t MAX_COPY_STREAMS = 4;
+    static constexpr uint32_t MAX_COPY_STREAMS = 8;
     hipStream_t s_copy[MAX_COPY_STREAMS] = {};
     uint32_t n_copy = 1;
     hipStream_t s_compute = nullptr, s_d2h = nullptr;

@@ -99,7 +99,7 @@ def test_errors(gkctx):
                          (gk.GK_OPT_HOST_CHUNK_PAIRS, 63),
                          (gk.GK_OPT_HOST_CHUNK_PAIRS, (1 << 26) + 1),
                          (gk.GK_OPT_SERVER_COPY_STREAMS, 0),
-                         (gk.GK_OPT_SERVER_COPY_STREAMS, 5), (999, 0)):
+                         (gk.GK_OPT_SERVER_COPY_STREAMS, 9), (999, 0)):
             with pytest.raises(gk.GkError) as ei:
                 gk.gk_set_option(ctx2, opt, val)
             assert ei.value.status == gk.GK_EINVAL
