@@ -432,7 +432,8 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream, uint64_t sam
  * GK_SERVER_BATCHED: requests are admitted in arrival order when a slot is
  * free and the device arena (device_budget_bytes, allocated at start) has
  * room for the request's footprint; admitted requests are copied in and
- * encoded on a copy stream while earlier ones are filtered, and every
+ * encoded on copy streams taken in turn (GK_OPT_SERVER_COPY_STREAMS) while
+ * earlier ones are filtered, and every
  * scheduling tick filters parts of the loaded requests together in one
  * persistent launch (the mixed-batch kernel over a table of parts, replayed
  * from a hipGraph), with at most two ticks in flight.  A tick takes the
@@ -442,8 +443,8 @@ int gk_tune_mixed(gk_ctx *ctx, const gk_batch *batch, void *stream, uint64_t sam
  * the small ones loaded after it.  Each part's results are copied back as
  * its tick completes; a request's slot and memory are freed after its last
  * part.  The tick's launch uses the context's mixed-batch tuning
- * (GK_OPT_MIXED_*, e.g. as gk_tune_mixed chose it) and the two server
- * options as they are when gk_server_start is called.
+ * (GK_OPT_MIXED_*, e.g. as gk_tune_mixed chose it) and the server options
+ * (GK_OPT_SERVER_*) as they are when gk_server_start is called.
  * GK_SERVER_SEQUENTIAL: the per-request baseline: one request at a time, copy
  * in, encode, one plain filter launch, copy out, on one stream.
  * Both give the same bytes as gk_filter on the same pairs.
