@@ -218,6 +218,13 @@ def encode_bytes_per_read(m: int, rows: int) -> int:
     return m + 8 + 4 * rows + 2 + 1
 
 
+def fused_bytes_per_pair(m: int) -> int:
+    """Algorithmic HBM bytes per pair of gk_filter_ascii (pair i uses read i):
+    the ASCII text (m B) and its offset (8 B), the window (m/4 B), the
+    position (4 B) in; accept + est (3 B) out."""
+    return m + 8 + m // 4 + 4 + 3
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +411,34 @@ def main() -> int:
                           and torch.equal(len2[:nr], dr.read_len[:nr])
                           and torch.equal(hn2[:nr], dr.has_n[:nr]))
         res_mism = int(np.sum((a2 != a_ref) | (s2 != s_ref)))
+        # The same work in one launch (gk_filter_ascii): the reads are encoded
+        # into registers and never written to memory.
+        fused = None
+        if identity:
+            batch3 = gk.make_batch(n_reads=0, pitch=0, max_read_len=m, reads=None,
+                                   read_len=None, pair_read=None, cand_pos=dp.cand_pos,
+                                   accept=dp.accept, est=dp.est, n_pairs=n_pairs, e_uniform=e)
+
+            def fused_filter():
+                gk.gk_filter_ascii(ctx, batch3, d_ascii, d_off, stream)
+            dp.accept.fill_(0xEE)
+            fu_ms, fu_min, fu_med = events_ms(fused_filter, 10, stream, warm=3, stats=True)
+            a3, s3 = device.results(dp)
+            fb = fused_bytes_per_pair(m)
+            fu_gbs = fb * n_pairs / (fu_ms / 1e3) / 1e9
+            fused = {"pairs_per_s": round(n_pairs / (fu_ms / 1e3), 1),
+                     "ms_per_step": round(fu_ms, 4), "ms_min": round(fu_min, 4),
+                     "ms_median": round(fu_med, 4), "runs": 10,
+                     "kernel": f"k_filter_ascii<{(rows + 1) // 2}, false>",
+                     "bytes_per_pair": fb, "achieved_gbs": round(fu_gbs, 1),
+                     "hbm_frac": round(fu_gbs / HBM_PEAK_GBS, 4),
+                     "mismatches_vs_kernel_path": int(np.sum((a3 != a_ref) | (s3 != s_ref))),
+                     "what": "gk_filter_ascii per run: ASCII reads encoded in the filter's "
+                             "own launch, HIP events on the launch stream"}
+            log(f"device-encoded fused: {fu_ms:.4f} ms "
+                f"({n_pairs / (fu_ms / 1e3) / 1e9:.2f} G pairs/s, {fu_gbs:.0f} GB/s), "
+                f"{fused['mismatches_vs_kernel_path']} result mismatches")
+            del batch3
         eb = encode_bytes_per_read(m, rows) * ps.n_reads
         enc_gbs = eb / (enc_ms / 1e3) / 1e9
         dev_enc = {"pairs_per_s": round(n_pairs / (ef_ms / 1e3), 1),
@@ -415,6 +450,7 @@ def main() -> int:
                                        "achieved": round(enc_gbs, 1), "peak": HBM_PEAK_GBS,
                                        "unit": "GB/s", "frac": round(enc_gbs / HBM_PEAK_GBS, 4),
                                        "bytes_per_read": encode_bytes_per_read(m, rows)},
+                   "fused": fused,
                    "words_identical_to_resident": same_words,
                    "mismatches_vs_kernel_path": res_mism,
                    "what": "ASCII reads + offsets resident in HBM: gk_encode_reads then "

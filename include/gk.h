@@ -124,7 +124,8 @@ int gk_reference_info(const gk_ctx *ctx, uint64_t *len, uint64_t *n_unknown);
  * Read encoding (Sec. 3.3: reads are 2-bit encoded, 16 bases per 32-bit word).
  *
  * ascii, read_off: DEVICE.  Read r is ascii[read_off[r] .. read_off[r+1]),
- * read_off has n_reads + 1 entries.
+ * read_off has n_reads + 1 entries; a read whose end offset is below its
+ * start is empty (length 0).
  * packed_out: DEVICE, rows * pitch words.  Word w of read r is written at
  * packed_out[w * pitch + r] (transposed, so a wavefront's loads coalesce)
  * and holds bases 16w .. 16w+15 in the given layout (GK_READS_*); code bits
@@ -205,6 +206,30 @@ typedef struct gk_batch {
  * for n_pairs >= 2^38.
  */
 int gk_filter(gk_ctx *ctx, const gk_batch *batch, void *stream);
+
+/*
+ * Filter that encodes its reads in the same launch: the paper's
+ * device-encoded mode, where the kernel encodes the sequences it is handed
+ * in ASCII (Sec. 3.3; the device-encoded rows of Table 2).  Pair i compares
+ * read i (one candidate per read) with ref[cand_pos[i], cand_pos[i] + m);
+ * the 2-bit reads are never written to memory.
+ *
+ * batch: as for gk_filter, except that pair_read must be NULL and the read
+ * fields (n_reads, pitch, reads, read_len, read_has_n, read_layout) are not
+ * used.
+ * ascii: DEVICE, 16-byte aligned.  Read i is ascii[read_off[i] ..
+ * read_off[i+1]); read_off: DEVICE, n_pairs + 1 entries.  As for
+ * gk_encode_reads, an end offset below the start gives an empty read, a
+ * read's length is capped at 0xFFFF, and a byte other
+ * than A/C/G/T (either case) in a read of length 1..max_read_len makes its
+ * pair GK_UNDEFINED.
+ * Results and accept bits equal those of gk_encode_reads (split layout,
+ * rows = ceil(max_read_len / 16)) followed by gk_filter on the same reads.
+ * Asynchronous on stream.  Errors as gk_filter, plus GK_EINVAL for a
+ * non-NULL pair_read, a NULL ascii or read_off, or an unaligned ascii.
+ */
+int gk_filter_ascii(gk_ctx *ctx, const gk_batch *batch, const uint8_t *ascii,
+                    const uint64_t *read_off, void *stream);
 
 /*
  * Host-to-host filter: the whole path from reads in host memory to results

@@ -15,8 +15,8 @@ CALIB_LIB = os.path.join(HERE, "libgk_calib.so")   # roofline calibration kernel
 CALIB_SOURCES = ["gk_calib.hip"]
 LOADGEN_LIB = os.path.join(HERE, "libgk_loadgen.so")  # served-bench load generator
 LOADGEN_SOURCES = ["gk_loadgen.cpp"]                   # host-only, links libgk.so
-SOURCES = ["gk_api.hip", "gk_encode.hip", "gk_filter.hip", "gk_host.hip", "gk_mixed.hip",
-           "gk_reference.hip", "gk_server.hip", "gk_verify.hip"]
+SOURCES = ["gk_api.hip", "gk_encode.hip", "gk_filter.hip", "gk_fused.hip", "gk_host.hip",
+           "gk_mixed.hip", "gk_reference.hip", "gk_server.hip", "gk_verify.hip"]
 HOST_SOURCES = ["gk_host_encode.cpp"]     # host-only C++ (no device code)
 ARCH = os.environ.get("GK_OFFLOAD_ARCH", "gfx950")
 

@@ -730,6 +730,46 @@ int gk_filter(gk_ctx *ctx, const gk_batch *b, void *stream)
     return GK_OK;
 }
 
+int gk_filter_ascii(gk_ctx *ctx, const gk_batch *b, const uint8_t *ascii,
+                    const uint64_t *read_off, void *stream)
+{
+    gkd::TraceRange trace("gk_filter_ascii");
+    if (!ctx)
+        return GK_EINVAL;
+    if (!b)
+        return fail(ctx, GK_EINVAL, "gk_filter_ascii: batch is NULL");
+    if (b->pair_read)
+        return fail(ctx, GK_EINVAL, "gk_filter_ascii: pair_read must be NULL (pair i uses read i)");
+    // The batch's read fields are not used: the reads come as text.
+    gk_batch bb = *b;
+    bb.n_reads = 0;
+    bb.pitch = 0;
+    bb.reads = nullptr;
+    bb.read_len = nullptr;
+    bb.read_has_n = nullptr;
+    bb.read_layout = GK_READS_SPLIT;
+    gkd::FilterArgs a{};
+    const int st = prepare_batch(ctx, &bb, "gk_filter_ascii", a);
+    if (st != GK_OK)
+        return st == 1 ? GK_OK : st;
+    if (!ascii || !read_off)
+        return fail(ctx, GK_EINVAL, "gk_filter_ascii: NULL ascii or read_off");
+    if ((uintptr_t)ascii & 15u)
+        return fail(ctx, GK_EINVAL, "gk_filter_ascii: ascii must be 16-byte aligned");
+    DeviceGuard g(ctx->device);
+    if (!g.ok)
+        return fail(ctx, GK_EDEVICE, "gk_filter_ascii: hipSetDevice failed");
+    const uint32_t words = (b->max_read_len + 31) / 32;
+    gk_detail_log(ctx, "gk_filter_ascii: %llu pairs, %u words per mask, e %s, flags %u",
+                  (unsigned long long)b->n_pairs, words, b->e ? "per pair" : "uniform",
+                  b->flags);
+    const hipError_t e =
+        gkd::launch_filter_ascii(a, words, ascii, read_off, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(ctx, e, "gk_filter_ascii: launch");
+    return GK_OK;
+}
+
 int gk_verify(gk_ctx *ctx, const gk_batch *b, const uint8_t *accept, uint16_t *dist,
               void *stream)
 {

@@ -194,6 +194,11 @@ hipError_t launch_accept_bits(const uint8_t *accept, uint64_t n, unsigned long l
                               hipStream_t s);
 size_t mixed_lds_size(uint32_t tile);
 
+// Launch the filter that encodes its own reads (pair i uses read i, read i
+// is ascii[read_off[i], read_off[i+1])), `words` 32-base words per mask.
+hipError_t launch_filter_ascii(const FilterArgs &a, uint32_t words, const uint8_t *ascii,
+                               const uint64_t *read_off, hipStream_t s);
+
 // Launch the plain filter with `words` 32-base words per mask (1..16).
 hipError_t launch_filter(const FilterArgs &a, uint32_t words, uint32_t layout,
                          uint32_t pairs_per_lane, hipStream_t s);

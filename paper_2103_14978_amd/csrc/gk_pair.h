@@ -188,10 +188,12 @@ __device__ __forceinline__ void load_read(const FilterArgs &a, uint32_t r, uint3
 
 // General path: any m <= 32W and any k <= m-1 <= 511.  Shifts of 32 bases or
 // more move whole words: the read planes are shifted in place by one word each
-// time k passes a multiple of 32, and reloaded between the deletion and the
-// insertion loop.
-template <int W, int L, bool REFINE = true>
+// time k passes a multiple of 32, and rebuilt between the deletion and the
+// insertion loop: reloaded from the read rows in memory, or, with KEPT (reads
+// that exist only in registers), taken again from the pair's words.
+template <int W, int L, bool REFINE = true, bool KEPT = false>
 __device__ __forceinline__ uint32_t filter_general(const FilterArgs &a, uint32_t r,
+                                                   const uint32_t (&words)[2 * W],
                                                    uint32_t (&rh)[W], uint32_t (&rl)[W],
                                                    const uint32_t (&gh)[W],
                                                    const uint32_t (&gl)[W], uint32_t m,
@@ -232,7 +234,13 @@ __device__ __forceinline__ uint32_t filter_general(const FilterArgs &a, uint32_t
         amend_and<W>(M, acc, X);
     }
 
-    load_read<W, L>(a, r, m, rh, rl);
+    if constexpr (KEPT) {
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            planes_from_words<L>(words[2 * w], words[2 * w + 1], rh[w], rl[w]);
+    } else {
+        load_read<W, L>(a, r, m, rh, rl);
+    }
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         rh[w] &= V[w];
@@ -299,19 +307,13 @@ __device__ __forceinline__ PairIdx load_idx(const FilterArgs &a, uint32_t i)
     return p;
 }
 
+// The window words of a pair: only those a window of up to max_read_len
+// bases can touch, from the copy of the planes in which they share one
+// 128-byte line.
 template <int W>
-__device__ __forceinline__ void load_data(const FilterArgs &a, const PairIdx &p, PairData<W> &d)
+__device__ __forceinline__ void load_window(const FilterArgs &a, uint32_t pos, PairData<W> &d)
 {
-    const uint32_t r = p.r < a.n_reads ? p.r : 0u;
-    const uint32_t pos = p.pos < a.ref_len ? p.pos : 0u;
-    d.m = a.n_reads ? (uint32_t)ld_once(a, a.read_len + r) : 0u;
-#pragma unroll
-    for (int j = 0; j < 2 * W; ++j) {
-        const uint32_t *row = a.reads + (size_t)j * a.pitch;
-        d.words[j] = (a.n_reads && (uint32_t)j < a.rows) ? ld_once(a, row + r) : 0u;
-    }
-    // Only the words a window of up to max_read_len bases can touch, from the
-    // copy of the planes in which they share one 128-byte line.
+    pos = pos < a.ref_len ? pos : 0u;
     const uint32_t w0 = pos >> 5;
     const uint32_t span = (pos & 31u) + a.max_read_len;
     const uint32_t nw = (span + 31u) >> 5;
@@ -321,6 +323,19 @@ __device__ __forceinline__ void load_data(const FilterArgs &a, const PairIdx &p,
 #pragma unroll
     for (int w = 0; w <= W; ++w)
         d.win[w] = 32u * w < span ? src[w] : make_uint2(0u, 0u);
+}
+
+template <int W>
+__device__ __forceinline__ void load_data(const FilterArgs &a, const PairIdx &p, PairData<W> &d)
+{
+    const uint32_t r = p.r < a.n_reads ? p.r : 0u;
+    d.m = a.n_reads ? (uint32_t)ld_once(a, a.read_len + r) : 0u;
+#pragma unroll
+    for (int j = 0; j < 2 * W; ++j) {
+        const uint32_t *row = a.reads + (size_t)j * a.pitch;
+        d.words[j] = (a.n_reads && (uint32_t)j < a.rows) ? ld_once(a, row + r) : 0u;
+    }
+    load_window<W>(a, p.pos, d);
 }
 
 // Whether a pair whose loads have arrived can be compared (Sec. 3.3): returns
@@ -385,8 +400,10 @@ __device__ __forceinline__ void pair_planes(const PairIdx &p, const PairData<W> 
 // guarantees 32(W-1) < m <= 32W and min(e, m-1) <= 31 for every valid pair,
 // and only the register-light fast path is compiled.  VAR compiles the
 // variant semantics of a.flags (GK_FLAG_*); without it a.flags must be 0, and
-// the paper's filter is the only code in the kernel.
-template <int W, int L, bool GENERAL = true, bool VAR = false>
+// the paper's filter is the only code in the kernel.  KEPT: the read has no
+// rows in memory (a.reads is not used), and the general path rebuilds its
+// planes from d.words.
+template <int W, int L, bool GENERAL = true, bool VAR = false, bool KEPT = false>
 __device__ __forceinline__ uint32_t compute_pair(const FilterArgs &a, const PairIdx &p,
                                                  const PairData<W> &d, uint32_t &est)
 {
@@ -418,12 +435,13 @@ __device__ __forceinline__ uint32_t compute_pair(const FilterArgs &a, const Pair
         }
         if (a.flags & GK_FLAG_NO_REFINE) {
             est = exact ? filter_exact<W, false>(rh, rl, gh, gl, m, kmax)
-                        : filter_general<W, L, false>(a, p.r, rh, rl, gh, gl, m, kmax);
+                        : filter_general<W, L, false, KEPT>(a, p.r, d.words, rh, rl, gh, gl,
+                                                                  m, kmax);
             return est <= p.e ? GK_ACCEPT : GK_REJECT;
         }
     }
     est = exact ? filter_exact<W>(rh, rl, gh, gl, m, kmax)
-                : filter_general<W, L>(a, p.r, rh, rl, gh, gl, m, kmax);
+                : filter_general<W, L, true, KEPT>(a, p.r, d.words, rh, rl, gh, gl, m, kmax);
     return est <= p.e ? GK_ACCEPT : GK_REJECT;
 }
 

@@ -154,6 +154,8 @@ def lib() -> ctypes.CDLL:
         L.gk_encode_reads.restype = i32
         L.gk_filter.argtypes = [vp, ctypes.POINTER(gk_batch), vp]
         L.gk_filter.restype = i32
+        L.gk_filter_ascii.argtypes = [vp, ctypes.POINTER(gk_batch), vp, vp, vp]
+        L.gk_filter_ascii.restype = i32
         L.gk_filter_host.argtypes = [vp, ctypes.POINTER(gk_host_batch)]
         L.gk_filter_host.restype = i32
         L.gk_verify.argtypes = [vp, ctypes.POINTER(gk_batch), vp, vp, vp]
@@ -191,7 +193,7 @@ def lib() -> ctypes.CDLL:
 
 EXPORTED = ("gk_create", "gk_destroy", "gk_last_error", "gk_load_reference",
             "gk_load_reference_2bit", "gk_reference_info", "gk_encode_reads", "gk_filter",
-            "gk_filter_host", "gk_verify", "gk_set_option",
+            "gk_filter_ascii", "gk_filter_host", "gk_verify", "gk_set_option",
             "gk_get_option", "gk_filter_mixed", "gk_filter_mixed_noalloc", "gk_tune_mixed",
             "gk_server_start", "gk_server_submit", "gk_server_wait", "gk_server_counters",
             "gk_server_tick_log", "gk_server_stop", "gk_clock_us")
@@ -316,6 +318,13 @@ def make_batch(*, n_reads, pitch, max_read_len, reads, read_len, pair_read, cand
 
 def gk_filter(ctx, batch: gk_batch, stream=None) -> None:
     _check(ctx, lib().gk_filter(ctx, ctypes.byref(batch), stream_handle(stream)), "gk_filter")
+
+
+def gk_filter_ascii(ctx, batch: gk_batch, ascii, read_off, stream=None) -> None:
+    """gk_filter with read i in ascii[read_off[i], read_off[i+1]) (device
+    tensors), encoded in the same launch; pair i uses read i."""
+    _check(ctx, lib().gk_filter_ascii(ctx, ctypes.byref(batch), ptr(ascii), ptr(read_off),
+                                      stream_handle(stream)), "gk_filter_ascii")
 
 
 def host_ptr(x):
