@@ -218,6 +218,10 @@ def encode_bytes_per_read(m: int, rows: int) -> int:
     return m + 8 + 4 * rows + 2 + 1
 
 
+# Sources of the fused encode + filter kernel (its counters are keyed on them).
+FUSED_SOURCES = ("gk_fused.hip", "gk_pair.h", "gk_args.h", "gk_encode_dev.h")
+
+
 def fused_bytes_per_pair(m: int) -> int:
     """Algorithmic HBM bytes per pair of gk_filter_ascii (pair i uses read i):
     the ASCII text (m B) and its offset (8 B), the window (m/4 B), the
@@ -426,12 +430,24 @@ def main() -> int:
             a3, s3 = device.results(dp)
             fb = fused_bytes_per_pair(m)
             fu_gbs = fb * n_pairs / (fu_ms / 1e3) / 1e9
+            fname = f"k_filter_ascii<{(rows + 1) // 2}"
+            fhash = kernel_source_hash(FUSED_SOURCES)
+            fprof = "k_filter_ascii_w4_config1_e5_counters.json"
+            f_traffic = traffic_from_profile(fhash, n_pairs, fprof, kernel=fname)
+            f_insts = traffic_from_profile(fhash, n_pairs, fprof, kernel=fname,
+                                           field="valu_insts_per_launch")
             fused = {"pairs_per_s": round(n_pairs / (fu_ms / 1e3), 1),
                      "ms_per_step": round(fu_ms, 4), "ms_min": round(fu_min, 4),
                      "ms_median": round(fu_med, 4), "runs": 10,
-                     "kernel": f"k_filter_ascii<{(rows + 1) // 2}, false>",
+                     "kernel": fname + ", false>",
                      "bytes_per_pair": fb, "achieved_gbs": round(fu_gbs, 1),
                      "hbm_frac": round(fu_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": f_traffic,
+                     "traffic_GBs": (round(f_traffic / (fu_ms / 1e3) / 1e9, 1)
+                                     if f_traffic else None),
+                     "valu_issued_Tops": (round(f_insts * 64 / (fu_ms / 1e3) / 1e12, 3)
+                                          if f_insts else None),
+                     "kernel_source_hash": fhash,
                      "mismatches_vs_kernel_path": int(np.sum((a3 != a_ref) | (s3 != s_ref))),
                      "what": "gk_filter_ascii per run: ASCII reads encoded in the filter's "
                              "own launch, HIP events on the launch stream"}
