@@ -98,6 +98,19 @@ def test_config1_full(gkctx, ref100m):
     check_properties(a, s, 5, 100, "config1")
     ra, rs = run_oracle(ref, ps.reads, ps.read_off, ps.pair_read, ps.cand_pos, 5)
     assert_same(a, s, ra, rs, "config1 every pair")
+    say("case: config1 full, reads encoded in the filter's launch (gk_filter_ascii)")
+    d_ascii = torch.from_numpy(np.ascontiguousarray(ps.reads)).cuda()
+    d_off = torch.from_numpy(ps.read_off.view(np.int64)).cuda()
+    dp2 = device.upload_pairs(None, ps.cand_pos)
+    dp2.accept.fill_(0xEE)
+    b2 = gk.make_batch(n_reads=0, pitch=0, max_read_len=100, reads=None, read_len=None,
+                       pair_read=None, cand_pos=dp2.cand_pos, accept=dp2.accept, est=dp2.est,
+                       e_uniform=5)
+    gk.gk_filter_ascii(gkctx, b2, d_ascii, d_off, None)
+    torch.cuda.synchronize()
+    a2, s2 = device.results(dp2)
+    assert_same(a2, s2, ra, rs, "config1 fused, every pair")
+    del d_ascii, d_off, dp2, b2, a2, s2
     say("case: config1 full verify of the accepted pairs")
     want = verify_check(gkctx, ref, ps, b, dp, a, 5, 1 << 15, 11, "config1 verify")
     assert np.any(want == 6)          # false accepts reach the cap
@@ -325,6 +338,21 @@ def test_beyond_2e30_identity(gkctx):
     a2, s2 = device.results(dp)
     assert np.array_equal(a2, a) and np.array_equal(s2, s), "mixed differs from plain"
     del a2, s2
+    # The same pairs with their reads as text: reads past the 4096th are
+    # empty (every later offset equals the text's end), so INVALID.
+    say(f"case: beyond 2^30 identity, gk_filter_ascii, n_pairs={n}")
+    d_ascii = torch.from_numpy(np.concatenate([reads, np.zeros(64, np.uint8)])).cuda()
+    d_off = torch.full((n + 1,), int(off[-1]), dtype=torch.int64, device="cuda")
+    d_off[:n_reads + 1] = torch.from_numpy(off.view(np.int64)).cuda()
+    b3 = gk.make_batch(n_reads=0, pitch=0, max_read_len=m, reads=None, read_len=None,
+                       pair_read=None, cand_pos=dp.cand_pos, accept=dp.accept, est=dp.est,
+                       n_pairs=n, e_uniform=e)
+    dp.accept.fill_(0xEE)
+    gk.gk_filter_ascii(gkctx, b3, d_ascii, d_off, None)
+    torch.cuda.synchronize()
+    a3, s3 = device.results(dp)
+    assert np.array_equal(a3, a) and np.array_equal(s3, s), "gk_filter_ascii differs from plain"
+    del a3, s3, d_ascii, d_off, b3
     dist = torch.empty(n, dtype=torch.int16, device="cuda")
     gk.gk_verify(gkctx, b, None, dist, None)
     torch.cuda.synchronize()
