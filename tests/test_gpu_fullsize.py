@@ -56,23 +56,29 @@ def sample_check(ref, ps, a, s, e, k, seed, label):
 def verify_check(ctx, ref, ps, b, dp, a, e, k, seed, label):
     """gk_verify after the filter, as the benchmark calls it: GK_EST_NONE on
     every pair the filter did not accept, at most e + 1 on every accepted
-    one, and the oracle's capped edit distance on a sample of the accepted."""
+    one, and the oracle's capped edit distance on a sample of the accepted.
+    e: one threshold, or one per pair."""
     dist = torch.empty(ps.n_pairs, dtype=torch.int16, device="cuda")
     gk.gk_verify(ctx, b, dp.accept, dist, None)
     torch.cuda.synchronize()
     d = dist.cpu().numpy().view(np.uint16)
     acc = a == gk.GK_ACCEPT
+    ea = np.broadcast_to(np.asarray(e, np.int64), (ps.n_pairs,))
     assert np.all(d[~acc] == gk.GK_EST_NONE), label
-    assert np.all(d[acc] <= e + 1), label
+    assert np.all(d[acc] <= ea[acc] + 1), label
     rng = np.random.default_rng(seed)
     idx = np.nonzero(acc)[0]
     idx = np.sort(rng.choice(idx, size=min(len(idx), k), replace=False))
-    want = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[idx],
-                                    ps.cand_pos[idx], e, n_threads=gen.default_threads())
+    want = np.empty(len(idx), np.uint16)
+    for v in np.unique(ea[idx]):
+        sel = ea[idx] == v
+        want[sel] = oracle.levenshtein_batch(ps.reads, ps.read_off, ref, ps.pair_read[idx[sel]],
+                                             ps.cand_pos[idx[sel]], int(v),
+                                             n_threads=gen.default_threads())
     bad = np.nonzero(d[idx] != want)[0]
     assert len(bad) == 0, (f"{label}: {len(bad)} of {len(idx)} differ; first pair "
                            f"{idx[bad[0]]}: gpu {d[idx[bad[0]]]} oracle {want[bad[0]]}")
-    assert np.any(want <= e), label
+    assert np.any(want <= ea[idx]), label
     return want
 
 
@@ -163,6 +169,9 @@ def test_config3_full(gkctx, ref100m):
     assert_same(a, s, a2, s2, "config3 mixed vs plain")
     sample_check(ref, ps, a, s, ps.e, 1 << 15, 3, "config3 sample")
     digest_check(a, s, "config3")
+    say("case: config3 full verify of the accepted pairs")
+    want = verify_check(gkctx, ref, ps, b, dp, a, ps.e, 1 << 15, 13, "config3 verify")
+    assert np.any(want == 0)
     for opt, val in ((gk.GK_OPT_MIXED_TILE, 4096), (gk.GK_OPT_MIXED_PAIRS_PER_LANE, 1),
                      (gk.GK_OPT_MIXED_SORT_E, 1), (gk.GK_OPT_MIXED_BLOCKS_PER_CU, 0)):
         gk.gk_set_option(gkctx, opt, val)

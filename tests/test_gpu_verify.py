@@ -305,3 +305,30 @@ def test_verify_interleaved_layout(gkctx):
     d1 = verify(gkctx, reads, off, pr, pos, e, 250, layout=gk.GK_READS_INTERLEAVED)
     want = oracle_dist(ref, reads, off, pr, pos, e)
     assert np.array_equal(d1, want)
+
+
+@pytest.mark.parametrize("identity", [False, True])
+def test_verify_decoys_per_pair_e(gkctx, identity):
+    """A per-pair e on reads of 40-300 bases: edited pairs (distances on both
+    sides of e) and pairs at unrelated positions (distance above e, capped at
+    e + 1), e over both band widths; reads from the row-major copy (pair_read
+    given) and in place (pair i on read i); then a smaller batch on the same
+    context buffers."""
+    rng = np.random.default_rng(6464 + identity)
+    ref = gen.c0_reference()
+    gk.gk_load_reference(gkctx, ref)
+    for n in (20000, 7000):
+        reads, off, pr, pos, e = edited_pairs(rng, ref, n, max_len=300, min_len=40)
+        lens = (off[1:] - off[:-1]).astype(np.int64)
+        decoy = rng.random(n) < 0.5
+        pos[decoy] = rng.integers(0, len(ref) - 300, int(decoy.sum())).astype(np.uint32)
+        say(f"case: verify decoys per-pair e, identity={identity}, n={n}")
+        d = verify(gkctx, reads, off, None if identity else pr, pos, e, 300)
+        want = oracle_dist(ref, reads, off, pr, pos, e)
+        bad = np.nonzero(d != want)[0]
+        assert len(bad) == 0, (f"{len(bad)} differ; first {bad[0]}: gpu {d[bad[0]]} oracle "
+                               f"{want[bad[0]]} e={e[bad[0]]} m={lens[bad[0]]}")
+        long_ = lens > 64
+        capped = d == e.astype(np.uint16) + 1
+        assert np.sum(long_ & capped & decoy) > n // 10      # decoys: above e
+        assert np.sum(long_ & ~capped) > n // 10              # within e
