@@ -43,8 +43,11 @@ __device__ __forceinline__ uint32_t word_direct(const uint8_t *ascii, uint64_t o
     return word;
 }
 
+// Up to 4 words per mask (reads of 128 bases) the paper's filter fits in 64
+// registers, so eight waves per SIMD.
 template <int W, bool VAR>
-__global__ __launch_bounds__(256) void k_filter_ascii(FilterArgs a, const uint8_t *ascii,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W <= 4 && !VAR ? 8 : 1)))
+void k_filter_ascii(FilterArgs a, const uint8_t *ascii,
                                                       const uint64_t *read_off)
 {
     extern __shared__ uint32_t fa_lds[];
