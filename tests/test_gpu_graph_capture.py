@@ -1,6 +1,6 @@
-"""Library launches recorded into a caller's HIP graph: gk_filter and
-gk_filter_mixed_noalloc (the entry point that allocates nothing, for callers
-under graph capture) captured on a torch graph stream, then replayed several
+"""Library launches recorded into a caller's HIP graph: gk_filter,
+gk_filter_ascii and gk_filter_mixed_noalloc (the entry point that allocates
+nothing, for callers under graph capture) captured on a torch graph stream, then replayed several
 times with the outputs cleared eagerly between replays.  Every replay equals
 the eager launch of the same batches and the oracle, element by element.
 The mixed batch holds pairs with more than 31 shifts, so the captured
@@ -39,14 +39,25 @@ def test_capture_and_replay(gkctx):
     dr_p = device.encode_reads(gkctx, plain.reads, plain.read_off, max_len=100)
     dp_p = device.upload_pairs(None, plain.cand_pos, with_bits=True)
     b_p = device.batch_for(dr_p, dp_p, e_uniform=4, max_read_len=100)
+    # the same pairs with their reads as text, encoded in the filter's launch
+    d_ascii = torch.from_numpy(np.concatenate([plain.reads, np.zeros(64, np.uint8)])).cuda()
+    d_off = torch.from_numpy(plain.read_off.view(np.int64)).cuda()
+    dp_a = device.upload_pairs(None, plain.cand_pos, with_bits=True)
+    b_a = gk.make_batch(n_reads=0, pitch=0, max_read_len=100, reads=None, read_len=None,
+                        pair_read=None, cand_pos=dp_a.cand_pos, accept=dp_a.accept,
+                        est=dp_a.est, e_uniform=4, accept_bits=dp_a.accept_bits)
     torch.cuda.synchronize()
 
     # eager launches: the expected bytes
     gk.gk_filter_mixed_noalloc(gkctx, b_m, None)
     gk.gk_filter(gkctx, b_p, None)
+    gk.gk_filter_ascii(gkctx, b_a, d_ascii, d_off, None)
     torch.cuda.synchronize()
     want_m = device.results(dp_m) + (dp_m.accept_bits.cpu().numpy(),)
     want_p = device.results(dp_p) + (dp_p.accept_bits.cpu().numpy(),)
+    got_a = device.results(dp_a) + (dp_a.accept_bits.cpu().numpy(),)
+    assert_same(got_a[0], got_a[1], want_p[0], want_p[1], "eager ascii vs plain")
+    assert np.array_equal(got_a[2], want_p[2]), "eager ascii accept bits"
     ra, rs = run_oracle(ref, mixed.reads, mixed.read_off, mixed.pair_read, mixed.cand_pos,
                         mixed.e)
     assert_same(want_m[0], want_m[1], ra, rs, "eager noalloc vs oracle")
@@ -54,12 +65,12 @@ def test_capture_and_replay(gkctx):
     assert_same(want_p[0], want_p[1], ra, rs, "eager plain vs oracle")
 
     def clear():
-        for dp in (dp_m, dp_p):
+        for dp in (dp_m, dp_p, dp_a):
             dp.accept.fill_(0xEE)
             dp.est.fill_(0x5A5A)
             dp.accept_bits.fill_(-1)
 
-    say("case: graph capture of gk_filter_mixed_noalloc + gk_filter")
+    say("case: graph capture of gk_filter_mixed_noalloc + gk_filter + gk_filter_ascii")
     clear()
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
@@ -67,6 +78,7 @@ def test_capture_and_replay(gkctx):
         s = torch.cuda.current_stream()
         gk.gk_filter_mixed_noalloc(gkctx, b_m, s)
         gk.gk_filter(gkctx, b_p, s)
+        gk.gk_filter_ascii(gkctx, b_a, d_ascii, d_off, s)
     torch.cuda.synchronize()
     for rep in range(4):
         clear()
@@ -79,6 +91,9 @@ def test_capture_and_replay(gkctx):
         assert np.array_equal(got_m[2], want_m[2]), f"replay {rep}: noalloc accept bits"
         assert_same(got_p[0], got_p[1], want_p[0], want_p[1], f"replay {rep}: plain")
         assert np.array_equal(got_p[2], want_p[2]), f"replay {rep}: plain accept bits"
+        got_a = device.results(dp_a) + (dp_a.accept_bits.cpu().numpy(),)
+        assert_same(got_a[0], got_a[1], want_p[0], want_p[1], f"replay {rep}: ascii")
+        assert np.array_equal(got_a[2], want_p[2]), f"replay {rep}: ascii accept bits"
         # eager work between replays, on the same scratch array
         gk.gk_filter_mixed_noalloc(gkctx, b_m, None)
         torch.cuda.synchronize()
