@@ -125,7 +125,9 @@ int gk_reference_info(const gk_ctx *ctx, uint64_t *len, uint64_t *n_unknown);
  *
  * ascii, read_off: DEVICE.  Read r is ascii[read_off[r] .. read_off[r+1]),
  * read_off has n_reads + 1 entries; a read whose end offset is below its
- * start is empty (length 0).
+ * start is empty (length 0).  The text is read in aligned 4-byte words, so
+ * the rest of the word that holds a read's last byte may be read (never
+ * past that word).
  * packed_out: DEVICE, rows * pitch words.  Word w of read r is written at
  * packed_out[w * pitch + r] (transposed, so a wavefront's loads coalesce)
  * and holds bases 16w .. 16w+15 in the given layout (GK_READS_*); code bits
@@ -218,7 +220,9 @@ int gk_filter(gk_ctx *ctx, const gk_batch *batch, void *stream);
  * fields (n_reads, pitch, reads, read_len, read_has_n, read_layout) are not
  * used.
  * ascii: DEVICE, 16-byte aligned.  Read i is ascii[read_off[i] ..
- * read_off[i+1]); read_off: DEVICE, n_pairs + 1 entries.  As for
+ * read_off[i+1]); read_off: DEVICE, n_pairs + 1 entries.  The launch reads
+ * the text in aligned 4-byte words, so it may read the rest of the word that
+ * holds a read's last byte (never past that word).  As for
  * gk_encode_reads, an end offset below the start gives an empty read, a
  * read's length is capped at 0xFFFF, and a byte other
  * than A/C/G/T (either case) in a read of length 1..max_read_len makes its
