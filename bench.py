@@ -680,6 +680,14 @@ def main() -> int:
                 "kernel_ms_min": round(float(np.min(kernel_ms)), 4),
                 "kernel_ms_median": round(float(np.median(kernel_ms)), 4),
                 "hbm_alg_GBs": round(bytes_per_pair(m) * n_pairs / k_avg_s / 1e9, 1),
+                # what binds the launch in fact: the 128 B lines it fetches
+                # (one per random window gather, plus the streamed reads)
+                "line_rate": ({"lines_per_launch": int(traffic // 128),
+                               "G_lines_per_s": round(traffic / 128 / k_avg_s / 1e9, 1),
+                               "what": "counted traffic / 128 B over the mean kernel time; "
+                                       "the random window gathers (one line per pair) hold "
+                                       "the launch near 50 G lines/s"}
+                              if traffic else None),
                 "kernel_source_hash": khash}
 
     cpu = None
